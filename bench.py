@@ -1,0 +1,200 @@
+"""Benchmark: full simulation and incremental update of a 24-qubit layered
+random circuit (200 levels of RX/RY/RZ on every qubit + a random CNOT
+matching; 100 batches of 1-4 random gate inserts/removals at uniform levels).
+
+A step = one modifier batch: apply the edits, run the incremental update
+(timed), then a full re-simulation of the modified circuit (timed) whose
+bytes must equal the incremental result.  ``value`` is the full simulation's
+achieved HBM throughput (algorithmic bytes / wall time of the full
+re-simulations).  The JSON line also carries the incremental p50/p99 latency
+and speedup, the complex64 tier, the pass kernel's roofline and the CPU
+oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def pct(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_tier(Q, W, wl, dtype, steps, warmup):
+    nets = [list(x) for x in wl.nets]
+    sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels)
+    sim.build(nets)
+    st = sim.update()
+    first_full = st
+    for _ in range(warmup):
+        sim.update(full=True)
+    inc_ms, full_ms, speed, bound = [], [], [], []
+    full_bytes = full_wall = 0.0
+    pass_ms, passes = 0.0, 0
+    mismatches = 0
+    gate_amp = 0
+    t0 = time.perf_counter()
+    for step in range(steps):
+        batch = wl.batches[step % len(wl.batches)]
+        for e in batch:
+            W.apply_edit(nets, e)
+            sim.apply_edit(e)
+        si = sim.update()
+        h_inc = sim.hash()
+        sf = sim.update(full=True)
+        h_full = sim.hash()
+        mismatches += int(h_inc != h_full)
+        inc_ms.append(si["wall_ms"])
+        full_ms.append(sf["wall_ms"])
+        speed.append(sf["wall_ms"] / max(si["wall_ms"], 1e-9))
+        bound.append(si["levels_total"] / max(si["levels_replayed"], 1))
+        full_bytes += sf["bytes"]
+        full_wall += sf["wall_ms"]
+        pass_ms += sf["kernel_ms"]
+        passes += sf["passes"]
+        gate_amp += sf["gate_amp_updates"]
+        if step % 20 == 0:
+            log("%s step %d inc %.2f ms full %.2f ms mode %d" % (dtype, step, si["wall_ms"], sf["wall_ms"], si["mode"]))
+    t1 = time.perf_counter()
+    out = {
+        "dtype": dtype,
+        "timed_s": t1 - t0,
+        "full_gbs": full_bytes / (full_wall * 1e-3) / 1e9,
+        "full_ms_p50": pct(full_ms, 50),
+        "inc_ms_p50": pct(inc_ms, 50),
+        "inc_ms_p99": pct(inc_ms, 99),
+        "speedup_p50": pct(speed, 50),
+        "speedup_bound_p50": pct(bound, 50),
+        "updates_per_s": steps / sum(x * 1e-3 for x in inc_ms),
+        "mismatches": mismatches,
+        "passes_per_full": passes / max(steps, 1),
+        "pass_avg_ms": pass_ms / max(passes, 1),
+        "pass_bytes": full_bytes / max(passes, 1),
+        "gate_amp_updates_per_s": gate_amp / (full_wall * 1e-3),
+        "first_full_ms": first_full["wall_ms"],
+    }
+    return sim, nets, out
+
+
+def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
+    """Time the CPU oracle (all host threads) on the first nets of the same
+    circuit, adding nets until about min_s seconds of work."""
+    from oracle import oracle
+
+    threads = oracle.max_threads()
+    psi = oracle.basis(wl.n)
+    gates = 0
+    used = 0
+    t0 = time.perf_counter()
+    for net in wl.nets[:max_nets]:
+        oracle.apply_gates(wl.n, psi, list(net), threads)
+        gates += len(net)
+        used += 1
+        if time.perf_counter() - t0 >= min_s:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": full_bytes_per_gate * gates / dt / 1e9,
+        "unit": "GB/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "first %d nets (%d gates) of the %d-qubit circuit, complex128, %.1f s on %d threads; value = the "
+                  "GPU plan's bytes for the same gates / oracle time" % (used, gates, wl.n, dt, threads),
+        "gate_amp_updates_per_s": gates * (1 << wl.n) / dt,
+        "full_sim_s_extrapolated": dt * W.count_gates(wl.nets) / gates,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2210_01076_amd import qtask as Q
+    from paper_2210_01076_amd import workloads as W
+
+    wl = W.config(2)
+    sim128, nets, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup)
+    r64 = None
+    if not args.no_c64:
+        sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup)
+        import numpy as np
+        from oracle import oracle
+        a = sim128.state()
+        b = sim64.state()
+        r64["max_abs_vs_c128"] = float(np.max(np.abs(a - b.astype(np.complex128))))
+        r64["fidelity_vs_c128"] = oracle.fidelity(a, b)
+        sim64.close()
+    sim128.close()
+
+    per_gate = r128["pass_bytes"] * r128["passes_per_full"] / W.count_gates(nets)
+    cpu = None if args.no_cpu else cpu_baseline(W, wl, per_gate)
+
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+    achieved = r128["pass_bytes"] / (r128["pass_avg_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "full-sim HBM GB/s vs peak; incremental update p50/p99 latency and speedup vs full re-sim",
+        "value": round(r128["full_gbs"], 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r128["timed_s"] * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "layered random circuit, 24 qubits, 200 levels (RX/RY/RZ on every qubit + random "
+                               "CNOT matching), 100 batches of 1-4 random gate inserts/removals; complex128",
+                   "qubits": 24, "levels": 200, "batches": 100, "ckpt_levels": 50},
+        "frac_of_peak": round(r128["full_gbs"] / HBM_PEAK_GBS, 4),
+        "full_ms_p50": r128["full_ms_p50"],
+        "incremental_ms_p50": r128["inc_ms_p50"],
+        "incremental_ms_p99": r128["inc_ms_p99"],
+        "incremental_speedup_p50": r128["speedup_p50"],
+        "replay_bound_speedup_p50": r128["speedup_bound_p50"],
+        "incremental_mismatches": r128["mismatches"],
+        "updates_per_s": {"c128": r128["updates_per_s"], "c64": r64["updates_per_s"] if r64 else None},
+        "gate_amp_updates_per_s": r128["gate_amp_updates_per_s"],
+        "passes_per_full_sim": r128["passes_per_full"],
+        "c64": r64,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "qk_pass<double>", "bytes_per_launch": r128["pass_bytes"],
+                     "avg_launch_ms": r128["pass_avg_ms"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,44 @@
+// Host-side launchers of the HIP kernels (kernels.hip).  All launches are
+// asynchronous on `s`; each returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kdefs.h"
+
+namespace qtask {
+
+// One pass over `n_tiles` tiles of 2^b amplitudes (dtype 0: complex128, 1: complex64).
+hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s);
+
+// Batched small-session pass round: `n_items` items, `n_groups` workgroups in
+// total, `max_threads` threads and `lds_bytes` LDS per workgroup.
+hipError_t launch_pass_batch(int dtype, const KBatchItem *items, uint32_t n_items, uint32_t n_groups,
+                             uint32_t max_threads, uint32_t lds_bytes, hipStream_t s);
+
+// FP64 sum |a_i|^2 over n elements: partial sums over a fixed grid, then one
+// workgroup adds them in a fixed order.  out[0] = sum; when scale_out is not
+// null, scale_out[0] = 1/sqrt(sum).
+uint32_t reduce_grid(uint64_t n);
+hipError_t launch_norm(int dtype, const void *state, uint64_t n, double *partials, double *out,
+                       double *scale_out, hipStream_t s);
+// Sum of n_partials precomputed partials (fixed order).
+hipError_t launch_sum_partials(const double *partials, uint32_t n_partials, double *out, double *scale_out,
+                               hipStream_t s);
+// <a|b> in FP64: out[0] = re, out[1] = im.  partials needs 2*reduce_grid(n) doubles.
+hipError_t launch_inner(int dtype, const void *a, const void *b, uint64_t n, double *partials, double *out,
+                        hipStream_t s);
+// state *= (R)scale[0]
+hipError_t launch_scale(int dtype, void *state, uint64_t n, const double *scale, hipStream_t s);
+// Count elements whose bytes differ.  partials needs reduce_grid(n) uint64.
+hipError_t launch_compare(int dtype, const void *a, const void *b, uint64_t n, unsigned long long *partials,
+                          unsigned long long *out, hipStream_t s);
+// Order-independent 64-bit hash of the state bytes.
+hipError_t launch_hash(int dtype, const void *a, uint64_t n, unsigned long long *partials,
+                       unsigned long long *out, hipStream_t s);
+// state = |0...0>
+hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s);
+// dst[block] = src[block] for the listed blocks of 2^block_bits elements.
+hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint32_t *blocks, uint32_t n_blocks,
+                              int block_bits, hipStream_t s);
+
+}  // namespace qtask

@@ -1,0 +1,99 @@
+// Plan records shared by the host planner and the HIP pass kernel.
+//
+// A segment plan is one contiguous device blob laid out as
+//   [KPass x n_pass][KStage x n_stage][KOp x n_op][coefficients (R) x n_coef]
+// Offsets inside records are relative to the start of their own array.
+//
+// A pass works on tiles of 2^b amplitudes.  Tile bit p (0 <= p < b) stands
+// for global qubit qlist[p]; qlist[0..c-1] = 0..c-1, so a tile is made of
+// 2^(b-c) chunks of 2^c contiguous amplitudes.  The remaining n-b global
+// bits enumerate the tiles.  Inside a workgroup the tile lives in LDS at a
+// swizzled slot phys(l) (a GF(2)-linear map of the tile index l, so every
+// offset below is an XOR of per-bit contributions).  A stage maps QK_G tile
+// bits onto the QK_NREG registers of each thread and the other b-QK_G tile
+// bits onto the thread index; its ops then run on registers.
+#pragma once
+#include <stdint.h>
+
+#define QK_G 4                // register bits per thread in a stage
+#define QK_NREG 16            // 2^QK_G amplitudes per thread
+#define QK_MAX_TILE_BITS 13
+#define QK_MIN_TILE_BITS 4
+#define QK_MAX_THR_BITS (QK_MAX_TILE_BITS - QK_G)
+#define QK_MAX_QUBITS 34
+#define QK_MAX_DENSE_K 6
+
+enum KOpType : uint8_t {
+    KOP_NONE = 0,
+    KOP_U1 = 1,    // dense 2x2 on bit a                         coef: m00 m01 m10 m11 (8 reals)
+    KOP_D1 = 2,    // diagonal on bit a                          coef: d0 d1 (4)
+    KOP_A1 = 3,    // anti-diagonal on bit a                     coef: m01 m10 (4)
+    KOP_X1 = 4,    // exact exchange on bit a                    coef: none
+    KOP_CU = 5,    // dense 2x2 on bit b where bit a = 1         coef: 8
+    KOP_CX = 6,    // exact exchange on bit b where bit a = 1    coef: none
+    KOP_D2 = 7,    // diagonal on (a,b), local 2*bit(a)+bit(b)   coef: d0..d3 (8)
+    KOP_SWAP = 8,  // exact exchange of bits a and b             coef: none
+    KOP_U2 = 9,    // dense 4x4 on (a,b), local 2*bit(a)+bit(b)  coef: 32
+    KOP_CCX = 10,  // exact exchange on bit c where a = b = 1    coef: none
+    KOP_DENSE = 11 // dense 16x16 on all QK_G register bits      coef: 512
+};
+
+enum KStageKind : uint32_t {
+    KSTAGE_LIST = 0,   // ops on registers (vector ALU)
+    KSTAGE_MFMA = 1    // one dense 2^k x 2^k unitary on the matrix cores
+};
+
+struct KOp {
+    uint8_t type, a, b, c;  // register bit positions (a = first-listed qubit = high local bit)
+    uint32_t coef;          // offset into the coefficient array (in R units)
+};
+
+struct KStage {
+    uint32_t reg_off[QK_NREG];        // LDS slot of register i relative to the thread base
+    uint32_t thr_off[QK_MAX_THR_BITS];// LDS slot contribution of thread-index bit k
+    uint32_t op_begin, op_count;
+    uint32_t kind;                    // KStageKind
+    uint32_t k;                       // MFMA stage: qubits of the dense unitary
+    uint32_t coef;                    // MFMA stage: offset of the 2^k x 2^k matrix (interleaved)
+    uint32_t n_col_bits;              // MFMA stage: b - k
+    uint32_t row_off[1 << QK_MAX_DENSE_K]; // MFMA stage: LDS slot of row r (the k stage bits)
+    uint32_t col_off[QK_MAX_TILE_BITS];    // MFMA stage: LDS slot contribution of column bit
+};
+
+struct KPass {
+    uint64_t g_i[QK_NREG];              // global offset of load register i
+    uint64_t g_thr[QK_MAX_THR_BITS];    // global offset contribution of thread bit k
+    uint32_t p_i[QK_NREG];              // LDS slot of load register i
+    uint32_t p_thr[QK_MAX_THR_BITS];    // LDS slot contribution of thread bit k
+    uint8_t nonq_pos[QK_MAX_QUBITS];    // global bit of tile-index bit k
+    uint8_t pad[2];
+    uint32_t n_nonq;                    // n - b
+    uint32_t n_thr;                     // b - QK_G
+    uint32_t stage_begin, stage_count;
+};
+
+// Launch arguments of one pass (passed by value).
+struct KArgs {
+    void *dst;                 // state written by the pass
+    const void *src;           // state read by the pass (may equal dst)
+    void *ckpt;                // optional second destination (checkpoint), or null
+    const KPass *pass;
+    const KStage *stages;
+    const KOp *ops;
+    const void *coefs;         // R array
+    const uint32_t *tile_list; // optional: blockIdx -> tile index
+    const uint64_t *store_mask;// optional: store only blocks whose bit is set
+    const double *scale;       // optional: multiply loaded amplitudes by (R)*scale
+    double *partials;          // optional: per-tile sum |a|^2 in FP64 (indexed by blockIdx)
+    uint32_t src_basis;        // 1: the input is |0...0> (src unused)
+    uint32_t block_bits;       // store_mask granularity
+};
+
+// Work item of the batched small-session launch.
+struct KBatchItem {
+    KArgs args;
+    uint32_t tile_begin;       // first global workgroup index of this item
+    uint32_t n_tiles;
+    uint32_t threads;          // 2^(b - QK_G) threads used by this item
+    uint32_t pad;
+};

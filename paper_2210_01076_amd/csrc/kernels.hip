@@ -1,0 +1,713 @@
+// HIP kernels for gfx950 (CDNA4): the pass kernel that applies a planned
+// group of gates to every tile of the state, and the FP64 reductions.
+//
+// Pass kernel (one workgroup per tile of 2^b amplitudes, 2^(b-4) threads):
+//  1. load: each thread reads 16 amplitudes; consecutive lanes read
+//     consecutive addresses inside the tile's 2^c-amplitude chunks, so every
+//     wave issues fully used 16-byte-per-lane loads;
+//  2. the tile goes to LDS at swizzled slots (XOR of the low bits with a
+//     linear function of the high bits, so the strided register gathers of
+//     the stages below hit distinct banks);
+//  3. each stage gathers 16 amplitudes per thread spanning 4 tile qubits,
+//     runs its ops on registers (exact exchanges for X/CX/SWAP/CCX, phase
+//     scalings for diagonal gates, 2x2/4x4/16x16 complex matrices otherwise)
+//     and scatters them back;
+//  4. store, optionally also to a checkpoint buffer, optionally only the
+//     blocks of an affected-block mask, optionally accumulating the FP64
+//     squared norm of the tile.
+// All arithmetic is in the state's precision (FP64 for complex128, FP32 for
+// complex64); there are no atomics, so every result is a pure function of
+// the input and the plan.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace qtask {
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+#define NR QK_NREG
+
+// ------------------------------------------------------------ register ops
+template <int A, typename R>
+__device__ __forceinline__ void op_u1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R m00r = c[0], m00i = c[1], m01r = c[2], m01i = c[3];
+    const R m10r = c[4], m10i = c[5], m11r = c[6], m11i = c[7];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & (1 << A)) continue;
+        const int j = i | (1 << A);
+        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
+        re[i] = m00r * xr - m00i * xi + m01r * yr - m01i * yi;
+        im[i] = m00r * xi + m00i * xr + m01r * yi + m01i * yr;
+        re[j] = m10r * xr - m10i * xi + m11r * yr - m11i * yi;
+        im[j] = m10r * xi + m10i * xr + m11r * yi + m11i * yr;
+    }
+}
+
+template <int A, typename R>
+__device__ __forceinline__ void op_d1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R d0r = c[0], d0i = c[1], d1r = c[2], d1i = c[3];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const R dr = (i & (1 << A)) ? d1r : d0r;
+        const R di = (i & (1 << A)) ? d1i : d0i;
+        const R xr = re[i], xi = im[i];
+        re[i] = dr * xr - di * xi;
+        im[i] = dr * xi + di * xr;
+    }
+}
+
+template <int A, typename R>
+__device__ __forceinline__ void op_a1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R ar = c[0], ai = c[1], br = c[2], bi = c[3];  // m01, m10
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & (1 << A)) continue;
+        const int j = i | (1 << A);
+        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
+        re[i] = ar * yr - ai * yi;
+        im[i] = ar * yi + ai * yr;
+        re[j] = br * xr - bi * xi;
+        im[j] = br * xi + bi * xr;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void swap_amp(R (&re)[NR], R (&im)[NR], int i, int j) {
+    const R tr = re[i], ti = im[i];
+    re[i] = re[j]; im[i] = im[j];
+    re[j] = tr; im[j] = ti;
+}
+
+template <int A, typename R>
+__device__ __forceinline__ void op_x1(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if (!(i & (1 << A))) swap_amp(re, im, i, i | (1 << A));
+}
+
+template <int A, int B, typename R>
+__device__ __forceinline__ void op_cu(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R m00r = c[0], m00i = c[1], m01r = c[2], m01i = c[3];
+    const R m10r = c[4], m10i = c[5], m11r = c[6], m11i = c[7];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (!(i & (1 << A)) || (i & (1 << B))) continue;
+        const int j = i | (1 << B);
+        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
+        re[i] = m00r * xr - m00i * xi + m01r * yr - m01i * yi;
+        im[i] = m00r * xi + m00i * xr + m01r * yi + m01i * yr;
+        re[j] = m10r * xr - m10i * xi + m11r * yr - m11i * yi;
+        im[j] = m10r * xi + m10i * xr + m11r * yi + m11i * yr;
+    }
+}
+
+template <int A, int B, typename R>
+__device__ __forceinline__ void op_cx(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if ((i & (1 << A)) && !(i & (1 << B))) swap_amp(re, im, i, i | (1 << B));
+}
+
+template <int A, int B, typename R>
+__device__ __forceinline__ void op_d2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    R dr[4], di[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) { dr[l] = c[2 * l]; di[l] = c[2 * l + 1]; }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int l = (((i >> A) & 1) << 1) | ((i >> B) & 1);
+        const R xr = re[i], xi = im[i];
+        re[i] = dr[l] * xr - di[l] * xi;
+        im[i] = dr[l] * xi + di[l] * xr;
+    }
+}
+
+template <int A, int B, typename R>
+__device__ __forceinline__ void op_swap(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if ((i & (1 << A)) && !(i & (1 << B))) swap_amp(re, im, i, (i & ~(1 << A)) | (1 << B));
+}
+
+template <int A, int B, typename R>
+__device__ __forceinline__ void op_u2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if ((i & (1 << A)) || (i & (1 << B))) continue;
+        const int idx[4] = {i, i | (1 << B), i | (1 << A), i | (1 << A) | (1 << B)};
+        R xr[4], xi[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) { xr[l] = re[idx[l]]; xi[l] = im[idx[l]]; }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            R sr = 0, si = 0;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const R mr = c[2 * (4 * r + l)], mi = c[2 * (4 * r + l) + 1];
+                sr += mr * xr[l] - mi * xi[l];
+                si += mr * xi[l] + mi * xr[l];
+            }
+            re[idx[r]] = sr;
+            im[idx[r]] = si;
+        }
+    }
+}
+
+template <int A, int B, int C, typename R>
+__device__ __forceinline__ void op_ccx(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if ((i & (1 << A)) && (i & (1 << B)) && !(i & (1 << C))) swap_amp(re, im, i, i | (1 << C));
+}
+
+template <typename R>
+__device__ __forceinline__ void op_dense(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    R xr[NR], xi[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) { xr[i] = re[i]; xi[i] = im[i]; }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        R sr = 0, si = 0;
+#pragma unroll
+        for (int l = 0; l < NR; ++l) {
+            const R mr = c[2 * (NR * r + l)], mi = c[2 * (NR * r + l) + 1];
+            sr += mr * xr[l] - mi * xi[l];
+            si += mr * xi[l] + mi * xr[l];
+        }
+        re[r] = sr;
+        im[r] = si;
+    }
+}
+
+#define SW1(F)                                   \
+    switch (op.a) {                              \
+    case 0: F<0>(re, im, c); break;              \
+    case 1: F<1>(re, im, c); break;              \
+    case 2: F<2>(re, im, c); break;              \
+    default: F<3>(re, im, c); break;             \
+    }
+
+#define SW2(F)                                   \
+    switch (op.a * 4 + op.b) {                   \
+    case 1: F<0, 1>(re, im, c); break;           \
+    case 2: F<0, 2>(re, im, c); break;           \
+    case 3: F<0, 3>(re, im, c); break;           \
+    case 4: F<1, 0>(re, im, c); break;           \
+    case 6: F<1, 2>(re, im, c); break;           \
+    case 7: F<1, 3>(re, im, c); break;           \
+    case 8: F<2, 0>(re, im, c); break;           \
+    case 9: F<2, 1>(re, im, c); break;           \
+    case 11: F<2, 3>(re, im, c); break;          \
+    case 12: F<3, 0>(re, im, c); break;          \
+    case 13: F<3, 1>(re, im, c); break;          \
+    case 14: F<3, 2>(re, im, c); break;          \
+    default: break;                              \
+    }
+
+// controls a < b, target c
+#define SW3(F)                                   \
+    switch (op.a * 16 + op.b * 4 + op.c) {       \
+    case 0 * 16 + 1 * 4 + 2: F<0, 1, 2>(re, im, c); break; \
+    case 0 * 16 + 1 * 4 + 3: F<0, 1, 3>(re, im, c); break; \
+    case 0 * 16 + 2 * 4 + 1: F<0, 2, 1>(re, im, c); break; \
+    case 0 * 16 + 2 * 4 + 3: F<0, 2, 3>(re, im, c); break; \
+    case 0 * 16 + 3 * 4 + 1: F<0, 3, 1>(re, im, c); break; \
+    case 0 * 16 + 3 * 4 + 2: F<0, 3, 2>(re, im, c); break; \
+    case 1 * 16 + 2 * 4 + 0: F<1, 2, 0>(re, im, c); break; \
+    case 1 * 16 + 2 * 4 + 3: F<1, 2, 3>(re, im, c); break; \
+    case 1 * 16 + 3 * 4 + 0: F<1, 3, 0>(re, im, c); break; \
+    case 1 * 16 + 3 * 4 + 2: F<1, 3, 2>(re, im, c); break; \
+    case 2 * 16 + 3 * 4 + 0: F<2, 3, 0>(re, im, c); break; \
+    case 2 * 16 + 3 * 4 + 1: F<2, 3, 1>(re, im, c); break; \
+    default: break;                              \
+    }
+
+template <typename R>
+__device__ __forceinline__ void apply_op(const KOp op, R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    switch (op.type) {
+    case KOP_U1: SW1(op_u1) break;
+    case KOP_D1: SW1(op_d1) break;
+    case KOP_A1: SW1(op_a1) break;
+    case KOP_X1: SW1(op_x1) break;
+    case KOP_CU: SW2(op_cu) break;
+    case KOP_CX: SW2(op_cx) break;
+    case KOP_D2: SW2(op_d2) break;
+    case KOP_SWAP: SW2(op_swap) break;
+    case KOP_U2: SW2(op_u2) break;
+    case KOP_CCX: SW3(op_ccx) break;
+    case KOP_DENSE: op_dense(re, im, c); break;
+    default: break;
+    }
+}
+
+// ---------------------------------------------------- deterministic reduce
+// Sum over the workgroup in a fixed order: a butterfly inside each wave,
+// then wave results added in wave order by thread 0.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *scratch) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += scratch[w];
+    }
+    return s;  // valid in thread 0
+}
+
+// -------------------------------------------------------------- pass body
+template <typename R>
+__device__ __forceinline__ void pass_body(uint32_t tile, uint32_t part_idx, void *dst_, const void *src_,
+                                          void *ckpt_, const KPass *__restrict__ P,
+                                          const KStage *__restrict__ stages, const KOp *__restrict__ ops,
+                                          const R *__restrict__ coefs, const uint64_t *__restrict__ store_mask,
+                                          const double *__restrict__ scale, double *__restrict__ partials,
+                                          uint32_t src_basis, uint32_t block_bits,
+                                          typename V2<R>::T *__restrict__ lds) {
+    using C = typename V2<R>::T;
+    const uint32_t t = threadIdx.x;
+    uint64_t base = 0;
+    const uint32_t n_nonq = P->n_nonq;
+    for (uint32_t k = 0; k < n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
+    const uint32_t n_thr = P->n_thr;
+    uint64_t gt = base;
+    uint32_t pt = 0;
+    for (uint32_t k = 0; k < n_thr; ++k)
+        if ((t >> k) & 1u) { gt |= P->g_thr[k]; pt ^= P->p_thr[k]; }
+
+    C v[NR];
+    if (src_basis) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const uint64_t idx = gt | P->g_i[i];
+            v[i].x = idx == 0 ? R(1) : R(0);
+            v[i].y = R(0);
+        }
+    } else {
+        const C *src = static_cast<const C *>(src_);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) v[i] = src[gt | P->g_i[i]];
+        if (scale) {
+            const R sc = R(scale[0]);
+#pragma unroll
+            for (int i = 0; i < NR; ++i) { v[i].x *= sc; v[i].y *= sc; }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) lds[pt ^ P->p_i[i]] = v[i];
+    __syncthreads();
+
+    const uint32_t ns = P->stage_count;
+    const KStage *st = stages + P->stage_begin;
+    for (uint32_t si = 0; si < ns; ++si) {
+        const KStage *S = st + si;
+        if (S->kind == KSTAGE_LIST) {
+            uint32_t bt = 0;
+            for (uint32_t k = 0; k < n_thr; ++k)
+                if ((t >> k) & 1u) bt ^= S->thr_off[k];
+            R re[NR], im[NR];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const C x = lds[bt ^ S->reg_off[i]];
+                re[i] = x.x;
+                im[i] = x.y;
+            }
+            const uint32_t oe = S->op_begin + S->op_count;
+            for (uint32_t oi = S->op_begin; oi < oe; ++oi) {
+                const KOp op = ops[oi];
+                apply_op<R>(op, re, im, coefs + op.coef);
+            }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                C x;
+                x.x = re[i];
+                x.y = im[i];
+                lds[bt ^ S->reg_off[i]] = x;
+            }
+        }
+        __syncthreads();
+    }
+
+    C *dst = static_cast<C *>(dst_);
+    C *ck = static_cast<C *>(ckpt_);
+    double acc = 0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const C x = lds[pt ^ P->p_i[i]];
+        const uint64_t idx = gt | P->g_i[i];
+        bool ok = true;
+        if (store_mask) {
+            const uint64_t blk = idx >> block_bits;
+            ok = (store_mask[blk >> 6] >> (blk & 63)) & 1;
+        }
+        if (ok) {
+            dst[idx] = x;
+            if (ck) ck[idx] = x;
+        }
+        if (partials) acc += double(x.x) * double(x.x) + double(x.y) * double(x.y);
+    }
+    if (partials) {
+        __shared__ double red[16];
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) partials[part_idx] = s;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(512)
+qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, const KStage *__restrict__ stages,
+        const KOp *__restrict__ ops, const R *__restrict__ coefs, const uint32_t *__restrict__ tile_list,
+        const uint64_t *__restrict__ store_mask, const double *__restrict__ scale, double *__restrict__ partials,
+        uint32_t src_basis, uint32_t block_bits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    using C = typename V2<R>::T;
+    const uint32_t tile = tile_list ? tile_list[blockIdx.x] : blockIdx.x;
+    pass_body<R>(tile, blockIdx.x, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale, partials,
+                 src_basis, block_bits, reinterpret_cast<C *>(smem));
+}
+
+// Batched pass round over many small sessions that share one tile shape:
+// each workgroup finds its item by binary search over the items' first
+// workgroup index.  Every decision below depends only on blockIdx, so a
+// workgroup either runs the whole pass body or leaves before any barrier.
+template <typename R>
+__global__ void __launch_bounds__(512)
+qk_pass_batch(const KBatchItem *__restrict__ items, uint32_t n_items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    using C = typename V2<R>::T;
+    uint32_t lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (items[mid].tile_begin <= blockIdx.x) lo = mid; else hi = mid;
+    }
+    const KBatchItem *it = items + lo;
+    const uint32_t local = blockIdx.x - it->tile_begin;
+    if (local >= it->n_tiles || it->threads != blockDim.x) return;
+    const KArgs &a = it->args;
+    const uint32_t tile = a.tile_list ? a.tile_list[local] : local;
+    pass_body<R>(tile, local, a.dst, a.src, a.ckpt, a.pass, a.stages, a.ops, static_cast<const R *>(a.coefs),
+                 a.store_mask, a.scale, a.partials, a.src_basis, a.block_bits, reinterpret_cast<C *>(smem));
+}
+
+// ------------------------------------------------------------- reductions
+constexpr int RED_THREADS = 256;
+
+uint32_t reduce_grid(uint64_t n) {
+    const uint64_t per = uint64_t(RED_THREADS) * 16;
+    uint64_t g = (n + per - 1) / per;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return uint32_t(g);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RED_THREADS) qk_norm_partials(const void *state_, uint64_t n, double *partials) {
+    using C = typename V2<R>::T;
+    const C *s = static_cast<const C *>(state_);
+    const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t beg = uint64_t(blockIdx.x) * chunk;
+    const uint64_t end = beg + chunk < n ? beg + chunk : n;
+    double acc = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += RED_THREADS) {
+        const C x = s[i];
+        acc += double(x.x) * double(x.x) + double(x.y) * double(x.y);
+    }
+    __shared__ double red[RED_THREADS / 64];
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RED_THREADS)
+qk_inner_partials(const void *a_, const void *b_, uint64_t n, double *partials) {
+    using C = typename V2<R>::T;
+    const C *a = static_cast<const C *>(a_);
+    const C *b = static_cast<const C *>(b_);
+    const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t beg = uint64_t(blockIdx.x) * chunk;
+    const uint64_t end = beg + chunk < n ? beg + chunk : n;
+    double re = 0, im = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += RED_THREADS) {
+        const C x = a[i], y = b[i];
+        const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+        re += xr * yr + xi * yi;
+        im += xr * yi - xi * yr;
+    }
+    __shared__ double red[RED_THREADS / 64];
+    const double tr = block_sum(re, red);
+    __syncthreads();
+    const double ti = block_sum(im, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = tr;
+        partials[2 * blockIdx.x + 1] = ti;
+    }
+}
+
+// One workgroup adds `n` partials (stride `stride`, offset `off`) in a fixed order.
+__global__ void __launch_bounds__(RED_THREADS)
+qk_sum_partials(const double *partials, uint32_t n, uint32_t stride, double *out, double *scale_out) {
+    double acc = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += RED_THREADS) acc += partials[size_t(i) * stride];
+    __shared__ double red[RED_THREADS / 64];
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        out[0] = tot;
+        if (scale_out) scale_out[0] = 1.0 / sqrt(tot);
+    }
+}
+
+template <typename R>
+__global__ void qk_scale(void *state_, uint64_t n, const double *scale) {
+    using C = typename V2<R>::T;
+    C *s = static_cast<C *>(state_);
+    const R sc = R(scale[0]);
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        C x = s[i];
+        x.x *= sc;
+        x.y *= sc;
+        s[i] = x;
+    }
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    // splitmix64 finaliser (Steele, Lea, Flood: "Fast splittable pseudorandom number generators")
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long *scratch) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < int((blockDim.x + 63) >> 6); ++w) s += scratch[w];
+    return s;
+}
+
+// Elements are compared / hashed as raw words: W = 2 (complex128) or 1
+// (complex64) 64-bit words per element.
+template <int W>
+__global__ void __launch_bounds__(RED_THREADS)
+qk_compare(const unsigned long long *a, const unsigned long long *b, uint64_t n, unsigned long long *partials) {
+    const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t beg = uint64_t(blockIdx.x) * chunk;
+    const uint64_t end = beg + chunk < n ? beg + chunk : n;
+    unsigned long long cnt = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += RED_THREADS) {
+        bool diff = false;
+#pragma unroll
+        for (int w = 0; w < W; ++w) diff |= a[W * i + w] != b[W * i + w];
+        cnt += diff ? 1 : 0;
+    }
+    __shared__ unsigned long long red[RED_THREADS / 64];
+    const unsigned long long tot = block_sum_u64(cnt, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+template <int W>
+__global__ void __launch_bounds__(RED_THREADS)
+qk_hash(const unsigned long long *a, uint64_t n, unsigned long long *partials) {
+    const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t beg = uint64_t(blockIdx.x) * chunk;
+    const uint64_t end = beg + chunk < n ? beg + chunk : n;
+    unsigned long long h = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += RED_THREADS) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) h += mix64(a[W * i + w] ^ mix64((W * i + w) * 0x9e3779b97f4a7c15ull + 1));
+    }
+    __shared__ unsigned long long red[RED_THREADS / 64];
+    const unsigned long long tot = block_sum_u64(h, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ void qk_sum_u64(const unsigned long long *partials, uint32_t n, unsigned long long *out) {
+    unsigned long long acc = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += RED_THREADS) acc += partials[i];
+    __shared__ unsigned long long red[RED_THREADS / 64];
+    const unsigned long long tot = block_sum_u64(acc, red);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+template <typename R>
+__global__ void qk_fill_basis(void *state_, uint64_t n) {
+    using C = typename V2<R>::T;
+    C *s = static_cast<C *>(state_);
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        C x;
+        x.x = i == 0 ? R(1) : R(0);
+        x.y = R(0);
+        s[i] = x;
+    }
+}
+
+template <typename R>
+__global__ void qk_copy_blocks(void *dst_, const void *src_, const uint32_t *blocks, uint32_t n_blocks,
+                               int block_bits) {
+    using C = typename V2<R>::T;
+    C *dst = static_cast<C *>(dst_);
+    const C *src = static_cast<const C *>(src_);
+    const uint64_t bsz = uint64_t(1) << block_bits;
+    for (uint32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
+        const uint64_t off = uint64_t(blocks[bi]) << block_bits;
+        for (uint64_t i = threadIdx.x; i < bsz; i += blockDim.x) dst[off + i] = src[off + i];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+namespace {
+template <typename R>
+void set_lds_limit() {
+    static bool done = false;
+    if (!done) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&qk_pass<R>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&qk_pass_batch<R>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        done = true;
+    }
+}
+
+uint32_t fill_grid(uint64_t n) {
+    uint64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    return uint32_t(g < 1 ? 1 : g);
+}
+}  // namespace
+
+hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
+    const uint32_t threads = 1u << (b - QK_G);
+    if (dtype == 0) {
+        set_lds_limit<double>();
+        const size_t lds = (size_t(1) << b) * sizeof(double2);
+        hipLaunchKernelGGL(qk_pass<double>, dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
+                           a.stages, a.ops, static_cast<const double *>(a.coefs), a.tile_list, a.store_mask,
+                           a.scale, a.partials, a.src_basis, a.block_bits);
+    } else {
+        set_lds_limit<float>();
+        const size_t lds = (size_t(1) << b) * sizeof(float2);
+        hipLaunchKernelGGL(qk_pass<float>, dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
+                           a.stages, a.ops, static_cast<const float *>(a.coefs), a.tile_list, a.store_mask,
+                           a.scale, a.partials, a.src_basis, a.block_bits);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_batch(int dtype, const KBatchItem *items, uint32_t n_items, uint32_t n_groups,
+                             uint32_t max_threads, uint32_t lds_bytes, hipStream_t s) {
+    if (dtype == 0) {
+        set_lds_limit<double>();
+        hipLaunchKernelGGL(qk_pass_batch<double>, dim3(n_groups), dim3(max_threads), lds_bytes, s, items, n_items);
+    } else {
+        set_lds_limit<float>();
+        hipLaunchKernelGGL(qk_pass_batch<float>, dim3(n_groups), dim3(max_threads), lds_bytes, s, items, n_items);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *partials, uint32_t n_partials, double *out, double *scale_out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(qk_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, partials, n_partials, 1u, out, scale_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(int dtype, const void *state, uint64_t n, double *partials, double *out, double *scale_out,
+                       hipStream_t s) {
+    const uint32_t g = reduce_grid(n);
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_norm_partials<double>, dim3(g), dim3(RED_THREADS), 0, s, state, n, partials);
+    else
+        hipLaunchKernelGGL(qk_norm_partials<float>, dim3(g), dim3(RED_THREADS), 0, s, state, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sum_partials(partials, g, out, scale_out, s);
+}
+
+hipError_t launch_inner(int dtype, const void *a, const void *b, uint64_t n, double *partials, double *out,
+                        hipStream_t s) {
+    const uint32_t g = reduce_grid(n);
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_inner_partials<double>, dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
+    else
+        hipLaunchKernelGGL(qk_inner_partials<float>, dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qk_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, partials, g, 2u, out, (double *)nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qk_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, partials + 1, g, 2u, out + 1,
+                       (double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int dtype, void *state, uint64_t n, const double *scale, hipStream_t s) {
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_scale<double>, dim3(fill_grid(n)), dim3(256), 0, s, state, n, scale);
+    else
+        hipLaunchKernelGGL(qk_scale<float>, dim3(fill_grid(n)), dim3(256), 0, s, state, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_compare(int dtype, const void *a, const void *b, uint64_t n, unsigned long long *partials,
+                          unsigned long long *out, hipStream_t s) {
+    const uint32_t g = reduce_grid(n);
+    const auto *pa = static_cast<const unsigned long long *>(a);
+    const auto *pb = static_cast<const unsigned long long *>(b);
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_compare<2>, dim3(g), dim3(RED_THREADS), 0, s, pa, pb, n, partials);
+    else
+        hipLaunchKernelGGL(qk_compare<1>, dim3(g), dim3(RED_THREADS), 0, s, pa, pb, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qk_sum_u64, dim3(1), dim3(RED_THREADS), 0, s, partials, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(int dtype, const void *a, uint64_t n, unsigned long long *partials, unsigned long long *out,
+                       hipStream_t s) {
+    const uint32_t g = reduce_grid(n);
+    const auto *pa = static_cast<const unsigned long long *>(a);
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_hash<2>, dim3(g), dim3(RED_THREADS), 0, s, pa, n, partials);
+    else
+        hipLaunchKernelGGL(qk_hash<1>, dim3(g), dim3(RED_THREADS), 0, s, pa, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qk_sum_u64, dim3(1), dim3(RED_THREADS), 0, s, partials, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s) {
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_fill_basis<double>, dim3(fill_grid(n)), dim3(256), 0, s, state, n);
+    else
+        hipLaunchKernelGGL(qk_fill_basis<float>, dim3(fill_grid(n)), dim3(256), 0, s, state, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint32_t *blocks, uint32_t n_blocks,
+                              int block_bits, hipStream_t s) {
+    if (n_blocks == 0) return hipSuccess;
+    const uint32_t g = n_blocks < 65535 ? n_blocks : 65535;
+    if (dtype == 0)
+        hipLaunchKernelGGL(qk_copy_blocks<double>, dim3(g), dim3(256), 0, s, dst, src, blocks, n_blocks, block_bits);
+    else
+        hipLaunchKernelGGL(qk_copy_blocks<float>, dim3(g), dim3(256), 0, s, dst, src, blocks, n_blocks, block_bits);
+    return hipGetLastError();
+}
+
+}  // namespace qtask

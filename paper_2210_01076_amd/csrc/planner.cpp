@@ -1,0 +1,501 @@
+// Pass and stage planning for one checkpoint segment.
+//
+// The paper partitions the state into blocks and runs each gate as tasks over
+// the blocks it touches (Section III-C).  On the GPU the same state is swept
+// in passes instead: a pass picks b qubits (the c lowest plus up to b-c
+// others), loads every tile of 2^b amplitudes spanned by them once into LDS,
+// applies every pending gate whose qubits all lie in that set, and writes the
+// tile back.  Gates are pulled into a pass as long as no earlier gate left
+// for later shares a qubit with them, so the program order of dependent
+// gates is kept while independent gates move freely (gates on disjoint
+// qubits commute; Section II-A lets parallel gates run in any order).
+// Inside a pass the gates are grouped into stages of at most QK_G qubits that
+// run on registers; consecutive one-qubit gates on the same qubit are merged
+// into one 2x2 matrix (FP64 product), and a stage whose gate list would cost
+// more than one dense unitary is fused into that unitary.
+#include "planner.h"
+
+#include <algorithm>
+#include <cstring>
+#include <sstream>
+#include <stdexcept>
+
+#include "../../include/qtask.h"
+
+namespace qtask {
+
+namespace {
+
+// Swizzle vectors XOR-ed into the low `swz` bits of an LDS slot for tile bit
+// j >= swz.  They are distinct, non-zero and not unit vectors, so any
+// choice of lane bits with linearly independent vectors is bank-conflict free.
+const uint32_t kSwz4[] = {3, 5, 6, 9, 10, 12, 7, 11, 13, 14, 15};
+const uint32_t kSwz5[] = {3, 5, 6, 9, 10, 12, 17, 18, 20, 24, 7, 11};
+
+uint32_t bank_vec(int p, int swz) {
+    if (p < swz) return 1u << p;
+    return swz == 4 ? kSwz4[p - 4] : kSwz5[p - 5];
+}
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// Order `bits` so the first ones have linearly independent bank vectors
+// (they become the low lane bits), then the rest ascending.
+std::vector<int> lane_order(const std::vector<int> &bits, int swz) {
+    std::vector<int> first, rest;
+    uint32_t basis[32] = {0};  // GF(2) echelon basis indexed by leading bit
+    for (int p : bits) {
+        uint32_t v = bank_vec(p, swz);
+        for (int lead = 31; lead >= 0 && v; --lead)
+            if (((v >> lead) & 1) && basis[lead]) v ^= basis[lead];
+        if (v != 0 && int(first.size()) < swz) {
+            basis[31 - __builtin_clz(v)] = v;
+            first.push_back(p);
+        } else {
+            rest.push_back(p);
+        }
+    }
+    first.insert(first.end(), rest.begin(), rest.end());
+    return first;
+}
+
+bool mergeable(const LGate &g) {
+    return g.nq == 1 && (g.kop == KOP_U1 || g.kop == KOP_D1 || g.kop == KOP_A1);
+}
+
+void set_1q_coef(LGate &g) {
+    g.coef.clear();
+    auto push = [&](cd z) { g.coef.push_back(z.real()); g.coef.push_back(z.imag()); };
+    if (g.kop == KOP_D1) { push(g.m[0]); push(g.m[3]); }
+    else if (g.kop == KOP_A1) { push(g.m[1]); push(g.m[2]); }
+    else for (int i = 0; i < 4; ++i) push(g.m[i]);
+}
+
+// later * earlier for two one-qubit gates on the same qubit
+LGate merge_1q(const LGate &later, const LGate &earlier) {
+    LGate r = earlier;
+    r.gate_id = 0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            r.m[i * 2 + j] = later.m[i * 2 + 0] * earlier.m[0 * 2 + j] + later.m[i * 2 + 1] * earlier.m[1 * 2 + j];
+    const bool ld = later.kop == KOP_D1, ed = earlier.kop == KOP_D1;
+    const bool la = later.kop == KOP_A1, ea = earlier.kop == KOP_A1;
+    if ((ld && ed) || (la && ea)) {
+        r.kop = KOP_D1; r.diagonal = true; r.monomial = true;
+        r.m[1] = r.m[2] = cd(0, 0);  // structural zeros stay exact
+    } else if ((ld && ea) || (la && ed)) {
+        r.kop = KOP_A1; r.diagonal = false; r.monomial = true;
+        r.m[0] = r.m[3] = cd(0, 0);
+    } else {
+        r.kop = KOP_U1; r.diagonal = false; r.monomial = false;
+    }
+    set_1q_coef(r);
+    return r;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &a, const std::vector<cd> &b, int dim) {
+    std::vector<cd> c(size_t(dim) * dim, cd(0, 0));
+    for (int i = 0; i < dim; ++i)
+        for (int k = 0; k < dim; ++k) {
+            const cd aik = a[size_t(i) * dim + k];
+            if (aik == cd(0, 0)) continue;
+            for (int j = 0; j < dim; ++j) c[size_t(i) * dim + j] += aik * b[size_t(k) * dim + j];
+        }
+    return c;
+}
+
+struct Packer {
+    const PlanParams &pp;
+    explicit Packer(const PlanParams &p) : pp(p) {}
+
+    int tile_bit_of(const PPass &ps, int q) const {
+        for (size_t p = 0; p < ps.qlist.size(); ++p)
+            if (ps.qlist[p] == q) return int(p);
+        throw std::logic_error("qubit not in pass");
+    }
+
+    // Build the stages of a pass from its ops (program order).
+    void pack_stages(PPass &ps, const std::vector<LGate> &ops) const {
+        const bool dense_mode = pp.fusion == QTASK_FUSE_DENSE;
+        const int W = dense_mode ? std::min(pp.fuse_k, pp.b) : QK_G;
+        std::vector<uint32_t> tmask(ops.size());
+        for (size_t i = 0; i < ops.size(); ++i) {
+            uint32_t m = 0;
+            for (int j = 0; j < ops[i].nq; ++j) m |= 1u << tile_bit_of(ps, ops[i].q[j]);
+            tmask[i] = m;
+        }
+        std::vector<size_t> rem(ops.size());
+        for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
+        while (!rem.empty()) {
+            uint32_t S = 0, blocked = 0;
+            std::vector<size_t> take, left;
+            for (size_t idx : rem) {
+                const uint32_t m = tmask[idx];
+                if (m & blocked) { blocked |= m; left.push_back(idx); continue; }
+                if (popc(S | m) <= W) { S |= m; take.push_back(idx); }
+                else { blocked |= m; left.push_back(idx); }
+            }
+            if (take.empty()) throw std::logic_error("stage packing made no progress");
+            for (int p = 0; p < pp.b && popc(S) < W; ++p) S |= 1u << p;
+            PStage st;
+            for (int p = 0; p < pp.b; ++p)
+                if ((S >> p) & 1) st.tbits.push_back(p);
+            std::vector<int> others;
+            for (int p = 0; p < pp.b; ++p)
+                if (!((S >> p) & 1)) others.push_back(p);
+            st.tpos = lane_order(others, pp.swz);
+            // ops, merging consecutive one-qubit gates on the same qubit
+            std::vector<int> last(pp.b, -1);
+            for (size_t idx : take) {
+                const LGate &g = ops[idx];
+                if (mergeable(g)) {
+                    const int tb = tile_bit_of(ps, g.q[0]);
+                    const int li = last[tb];
+                    if (li >= 0 && mergeable(st.ops[li])) {
+                        st.ops[li] = merge_1q(g, st.ops[li]);
+                        continue;
+                    }
+                }
+                st.ops.push_back(g);
+                for (int j = 0; j < g.nq; ++j) last[tile_bit_of(ps, g.q[j])] = int(st.ops.size()) - 1;
+            }
+            double fl = 0;
+            for (const auto &g : st.ops) fl += g.flops_per_amp();
+            st.flops = fl;
+            const double dense_fl = 8.0 * (1 << W) - 2;
+            bool make_dense = false;
+            if (dense_mode) {
+                make_dense = true;
+                st.mfma = W >= 4;  // the matrix-core stage needs k >= 4
+            } else if (pp.fusion == QTASK_FUSE_AUTO && fl > dense_fl) {
+                make_dense = true;  // dense 16x16 on registers is cheaper than the list
+            }
+            if (make_dense) {
+                std::vector<int> qs;
+                for (int p : st.tbits) qs.push_back(ps.qlist[p]);
+                const int dim = 1 << int(qs.size());
+                std::vector<cd> U(size_t(dim) * dim, cd(0, 0));
+                for (int i = 0; i < dim; ++i) U[size_t(i) * dim + i] = 1;
+                for (const auto &g : st.ops) U = matmul(embed(g, qs), U, dim);
+                st.U = U;
+                st.flops = dense_fl;
+            }
+            ps.stages.push_back(std::move(st));
+            rem.swap(left);
+        }
+    }
+
+    std::vector<PPass> pack_passes(const std::vector<LGate> &ops) const {
+        // keep room for a three-qubit gate on qubits above the low bits, so
+        // every pass can take at least the first pending gate
+        const int c = std::max(0, std::min(pp.c, pp.b - 3));
+        const uint64_t low = (uint64_t(1) << c) - 1;
+        std::vector<size_t> rem(ops.size());
+        for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
+        std::vector<PPass> passes;
+        while (!rem.empty()) {
+            uint64_t Q = low, blocked = 0;
+            std::vector<size_t> take, left;
+            for (size_t idx : rem) {
+                const uint64_t m = ops[idx].mask();
+                if (m & blocked) { blocked |= m; left.push_back(idx); continue; }
+                if (popc(Q | m) <= pp.b) { Q |= m; take.push_back(idx); }
+                else { blocked |= m; left.push_back(idx); }
+            }
+            if (take.empty()) throw std::logic_error("planner made no progress");
+            for (int q = 0; q < pp.n && popc(Q) < pp.b; ++q) Q |= uint64_t(1) << q;
+            PPass ps;
+            ps.qmask = Q;
+            for (int q = 0; q < pp.n; ++q)
+                if ((Q >> q) & 1) ps.qlist.push_back(q);
+            std::vector<LGate> pops;
+            for (size_t idx : take) pops.push_back(ops[idx]);
+            ps.n_gates = int(pops.size());
+            pack_stages(ps, pops);
+            passes.push_back(std::move(ps));
+            rem.swap(left);
+        }
+        return passes;
+    }
+};
+
+template <typename R>
+void pack_blob(SegmentPlan &sp) {
+    const PlanParams &pp = sp.pp;
+    const int b = pp.b, G = QK_G;
+    const int n_thr = b - G;
+    size_t n_stage = 0, n_op = 0, n_coef = 0;
+    for (const auto &ps : sp.passes)
+        for (const auto &st : ps.stages) {
+            ++n_stage;
+            if (st.mfma) n_coef += st.U.size() * 2;
+            else if (!st.U.empty()) { n_op += 1; n_coef += st.U.size() * 2; }
+            else for (const auto &g : st.ops) { ++n_op; n_coef += g.coef.size(); }
+        }
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t bytes_pass = align(sp.passes.size() * sizeof(KPass));
+    const size_t bytes_stage = align(n_stage * sizeof(KStage));
+    const size_t bytes_op = align(std::max<size_t>(n_op, 1) * sizeof(KOp));
+    const size_t bytes_coef = align(std::max<size_t>(n_coef, 1) * sizeof(R));
+    sp.off_stage = bytes_pass;
+    sp.off_op = bytes_pass + bytes_stage;
+    sp.off_coef = sp.off_op + bytes_op;
+    sp.blob.assign(sp.off_coef + bytes_coef, 0);
+    KPass *kp = reinterpret_cast<KPass *>(sp.blob.data());
+    KStage *ks = reinterpret_cast<KStage *>(sp.blob.data() + sp.off_stage);
+    KOp *ko = reinterpret_cast<KOp *>(sp.blob.data() + sp.off_op);
+    R *kc = reinterpret_cast<R *>(sp.blob.data() + sp.off_coef);
+    size_t si = 0, oi = 0, ci = 0;
+    auto phys = [&](int p) { return lds_phys(1u << p, pp.swz); };
+    for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
+        const PPass &ps = sp.passes[pi];
+        KPass &P = kp[pi];
+        std::memset(&P, 0, sizeof(P));
+        // load/store mapping: tile bits 0..n_thr-1 <- thread index, the top G bits <- register i
+        for (int k = 0; k < n_thr; ++k) {
+            P.g_thr[k] = uint64_t(1) << ps.qlist[k];
+            P.p_thr[k] = phys(k);
+        }
+        for (int i = 0; i < QK_NREG; ++i) {
+            uint64_t g = 0;
+            uint32_t p = 0;
+            for (int j = 0; j < G; ++j)
+                if ((i >> j) & 1) { g |= uint64_t(1) << ps.qlist[n_thr + j]; p ^= phys(n_thr + j); }
+            P.g_i[i] = g;
+            P.p_i[i] = p;
+        }
+        int k = 0;
+        for (int q = 0; q < pp.n; ++q)
+            if (!((ps.qmask >> q) & 1)) P.nonq_pos[k++] = uint8_t(q);
+        P.n_nonq = uint32_t(k);
+        P.n_thr = uint32_t(n_thr);
+        P.stage_begin = uint32_t(si);
+        P.stage_count = uint32_t(ps.stages.size());
+        for (const PStage &st : ps.stages) {
+            KStage &S = ks[si++];
+            std::memset(&S, 0, sizeof(S));
+            const int W = int(st.tbits.size());
+            if (st.mfma) {
+                S.kind = KSTAGE_MFMA;
+                S.k = uint32_t(W);
+                S.n_col_bits = uint32_t(b - W);
+                for (int r = 0; r < (1 << W); ++r) {
+                    uint32_t o = 0;
+                    for (int j = 0; j < W; ++j)
+                        if ((r >> j) & 1) o ^= phys(st.tbits[j]);
+                    S.row_off[r] = o;
+                }
+                for (int j = 0; j < b - W; ++j) S.col_off[j] = phys(st.tpos[j]);
+                S.coef = uint32_t(ci);
+                for (const cd &z : st.U) { kc[ci++] = R(z.real()); kc[ci++] = R(z.imag()); }
+                S.op_begin = uint32_t(oi);
+                S.op_count = 0;
+                continue;
+            }
+            S.kind = KSTAGE_LIST;
+            for (int i = 0; i < QK_NREG; ++i) {
+                uint32_t o = 0;
+                for (int j = 0; j < G; ++j)
+                    if ((i >> j) & 1) o ^= phys(st.tbits[j]);
+                S.reg_off[i] = o;
+            }
+            for (int j = 0; j < n_thr; ++j) S.thr_off[j] = phys(st.tpos[j]);
+            S.op_begin = uint32_t(oi);
+            auto reg_of = [&](int q) {
+                const int tb = [&] {
+                    for (size_t p = 0; p < ps.qlist.size(); ++p)
+                        if (ps.qlist[p] == q) return int(p);
+                    return -1;
+                }();
+                for (int j = 0; j < G; ++j)
+                    if (st.tbits[j] == tb) return j;
+                throw std::logic_error("op qubit outside its stage");
+            };
+            if (!st.U.empty()) {
+                KOp &o = ko[oi++];
+                o.type = KOP_DENSE;
+                o.a = o.b = o.c = 0;
+                o.coef = uint32_t(ci);
+                for (const cd &z : st.U) { kc[ci++] = R(z.real()); kc[ci++] = R(z.imag()); }
+            } else {
+                for (const LGate &g : st.ops) {
+                    KOp &o = ko[oi++];
+                    o.type = g.kop;
+                    o.a = uint8_t(reg_of(g.q[0]));
+                    o.b = g.nq > 1 ? uint8_t(reg_of(g.q[1])) : 0;
+                    o.c = g.nq > 2 ? uint8_t(reg_of(g.q[2])) : 0;
+                    if (g.kop == KOP_CCX && o.a > o.b) std::swap(o.a, o.b);
+                    o.coef = uint32_t(ci);
+                    for (double v : g.coef) kc[ci++] = R(v);
+                }
+            }
+            S.op_count = uint32_t(oi) - S.op_begin;
+        }
+    }
+}
+
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const uint8_t *b = static_cast<const uint8_t *>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+}  // namespace
+
+uint32_t lds_phys(uint32_t l, int swz) {
+    uint32_t x = l;
+    for (int j = swz; j < QK_MAX_TILE_BITS; ++j)
+        if ((l >> j) & 1) x ^= bank_vec(j, swz);
+    return x;
+}
+
+uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &pp, sizeof(pp));
+    for (const auto &g : ops) {
+        h = fnv(h, &g.kop, sizeof(g.kop));
+        h = fnv(h, g.q, sizeof(g.q));
+        for (const cd &z : g.m) h = fnv(h, &z, sizeof(z));
+    }
+    return h;
+}
+
+SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp) {
+    if (pp.b < QK_MIN_TILE_BITS || pp.b > QK_MAX_TILE_BITS || pp.b > pp.n || pp.c < 0 || pp.c > pp.b)
+        throw std::invalid_argument("plan parameters");
+    SegmentPlan sp;
+    sp.pp = pp;
+    Packer pk(pp);
+    sp.passes = pk.pack_passes(ops);
+    if (sp.passes.empty()) {
+        // a segment without gates still carries the state across its
+        // boundary (restore, checkpoint write, norm): one pass, no stages
+        PPass ps;
+        for (int q = 0; q < pp.b; ++q) {
+            ps.qlist.push_back(q);
+            ps.qmask |= uint64_t(1) << q;
+        }
+        sp.passes.push_back(ps);
+    }
+    sp.n_gates = ops.size();
+    for (const auto &ps : sp.passes)
+        for (const auto &st : ps.stages) sp.flops_per_amp += st.flops;
+    if (pp.dtype == 0) pack_blob<double>(sp);
+    else pack_blob<float>(sp);
+    sp.hash = segment_hash(ops, pp);
+    return sp;
+}
+
+std::string validate_plan(const SegmentPlan &sp) {
+    const PlanParams &pp = sp.pp;
+    const int b = pp.b, G = QK_G, n_thr = b - G;
+    const uint32_t tile = 1u << b;
+    std::ostringstream err;
+    const KPass *kp = reinterpret_cast<const KPass *>(sp.blob.data());
+    const KStage *ks = reinterpret_cast<const KStage *>(sp.blob.data() + sp.off_stage);
+    size_t gates = 0;
+    for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
+        const KPass &P = kp[pi];
+        const PPass &ps = sp.passes[pi];
+        gates += size_t(ps.n_gates);
+        if (int(ps.qlist.size()) != b) { err << "pass " << pi << ": qlist size"; return err.str(); }
+        for (int q = 0; q < std::max(0, std::min(pp.c, pp.b - 3)); ++q)
+            if (ps.qlist[q] != q) { err << "pass " << pi << ": low bits"; return err.str(); }
+        std::vector<uint8_t> seen(tile, 0);
+        uint64_t gmask = 0;
+        for (uint32_t t = 0; t < (1u << n_thr); ++t) {
+            uint32_t pt = 0;
+            uint64_t gt = 0;
+            for (int k = 0; k < n_thr; ++k)
+                if ((t >> k) & 1) { pt ^= P.p_thr[k]; gt |= P.g_thr[k]; }
+            for (int i = 0; i < QK_NREG; ++i) {
+                const uint32_t s = pt ^ P.p_i[i];
+                if (s >= tile || seen[s]++) { err << "pass " << pi << ": load map"; return err.str(); }
+                gmask |= gt | P.g_i[i];
+            }
+        }
+        if (gmask != ps.qmask) { err << "pass " << pi << ": global mask"; return err.str(); }
+        for (uint32_t s = 0; s < P.stage_count; ++s) {
+            const KStage &S = ks[P.stage_begin + s];
+            const PStage &st = ps.stages[s];
+            std::vector<uint8_t> seen2(tile, 0);
+            if (S.kind == KSTAGE_MFMA) {
+                for (uint32_t col = 0; col < (1u << S.n_col_bits); ++col) {
+                    uint32_t co = 0;
+                    for (uint32_t j = 0; j < S.n_col_bits; ++j)
+                        if ((col >> j) & 1) co ^= S.col_off[j];
+                    for (uint32_t r = 0; r < (1u << S.k); ++r) {
+                        const uint32_t sl = co ^ S.row_off[r];
+                        if (sl >= tile || seen2[sl]++) { err << "pass " << pi << " stage " << s << ": mfma map"; return err.str(); }
+                    }
+                }
+            } else {
+                for (uint32_t t = 0; t < (1u << n_thr); ++t) {
+                    uint32_t bt = 0;
+                    for (int k = 0; k < n_thr; ++k)
+                        if ((t >> k) & 1) bt ^= S.thr_off[k];
+                    for (int i = 0; i < QK_NREG; ++i) {
+                        const uint32_t sl = bt ^ S.reg_off[i];
+                        if (sl >= tile || seen2[sl]++) { err << "pass " << pi << " stage " << s << ": reg map"; return err.str(); }
+                    }
+                }
+            }
+            uint64_t sq = 0;
+            for (int p : st.tbits) sq |= uint64_t(1) << ps.qlist[p];
+            for (const auto &g : st.ops)
+                if ((g.mask() & ~sq) != 0) { err << "pass " << pi << " stage " << s << ": op outside stage"; return err.str(); }
+        }
+    }
+    if (gates != sp.n_gates) { err << "gate count " << gates << " != " << sp.n_gates; return err.str(); }
+    return "";
+}
+
+std::string plan_json(const SegmentPlan &sp, bool with_matrices) {
+    std::ostringstream o;
+    o.precision(17);
+    o << "{\"b\":" << sp.pp.b << ",\"c\":" << sp.pp.c << ",\"n\":" << sp.pp.n << ",\"dtype\":" << sp.pp.dtype
+      << ",\"fusion\":" << sp.pp.fusion << ",\"fuse_k\":" << sp.pp.fuse_k << ",\"gates\":" << sp.n_gates
+      << ",\"flops_per_amp\":" << sp.flops_per_amp << ",\"check\":\"" << validate_plan(sp) << "\",\"passes\":[";
+    for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
+        const PPass &ps = sp.passes[pi];
+        if (pi) o << ",";
+        o << "{\"qubits\":[";
+        for (size_t i = 0; i < ps.qlist.size(); ++i) o << (i ? "," : "") << ps.qlist[i];
+        o << "],\"gates\":" << ps.n_gates << ",\"stages\":[";
+        for (size_t si = 0; si < ps.stages.size(); ++si) {
+            const PStage &st = ps.stages[si];
+            if (si) o << ",";
+            o << "{\"qubits\":[";
+            for (size_t i = 0; i < st.tbits.size(); ++i) o << (i ? "," : "") << ps.qlist[st.tbits[i]];
+            o << "],\"mfma\":" << (st.mfma ? "true" : "false") << ",\"dense\":" << (st.U.empty() ? "false" : "true")
+              << ",\"flops_per_amp\":" << st.flops << ",\"ops\":[";
+            for (size_t k = 0; k < st.ops.size(); ++k) {
+                const LGate &g = st.ops[k];
+                if (k) o << ",";
+                o << "{\"kop\":" << int(g.kop) << ",\"gate\":" << g.gate_id << ",\"q\":[";
+                for (int j = 0; j < g.nq; ++j) o << (j ? "," : "") << g.q[j];
+                o << "]";
+                if (with_matrices) {
+                    o << ",\"m\":[";
+                    for (size_t z = 0; z < g.m.size(); ++z)
+                        o << (z ? "," : "") << "[" << g.m[z].real() << "," << g.m[z].imag() << "]";
+                    o << "]";
+                }
+                o << "}";
+            }
+            o << "]";
+            if (with_matrices && !st.U.empty()) {
+                o << ",\"U\":[";
+                for (size_t z = 0; z < st.U.size(); ++z)
+                    o << (z ? "," : "") << "[" << st.U[z].real() << "," << st.U[z].imag() << "]";
+                o << "]";
+            }
+            o << "}";
+        }
+        o << "]}";
+    }
+    o << "]}";
+    return o.str();
+}
+
+}  // namespace qtask

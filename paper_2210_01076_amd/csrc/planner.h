@@ -1,0 +1,69 @@
+// Planner: turns the ops of one checkpoint segment into passes over the
+// state (each pass = one read and one write of every tile) and, inside a
+// pass, into stages of register-resident work.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kdefs.h"
+#include "lowering.h"
+
+namespace qtask {
+
+struct PlanParams {
+    int n = 0;          // qubits of the state buffer (>= QK_MIN_TILE_BITS)
+    int b = 12;         // tile bits
+    int c = 4;          // contiguous low bits per tile
+    int dtype = 0;      // 0 complex128, 1 complex64
+    int fusion = 0;     // qtask_fusion
+    int fuse_k = 4;     // width of dense fused unitaries
+    int swz = 4;        // LDS swizzle width in bits
+};
+
+struct PStage {
+    std::vector<int> tbits;   // tile bits of the stage's register index bits (ascending)
+    std::vector<int> tpos;    // tile bits of the thread index (lane-friendly order)
+    std::vector<LGate> ops;   // ops in program order (global qubits)
+    bool mfma = false;        // one dense unitary on the matrix cores
+    std::vector<cd> U;        // fused unitary, register-index convention (MFMA and KOP_DENSE)
+    double flops = 0;         // algorithmic flops per amplitude
+};
+
+struct PPass {
+    std::vector<int> qlist;   // global qubit of tile bit p
+    std::vector<PStage> stages;
+    uint64_t qmask = 0;
+    int n_gates = 0;          // source gates applied in this pass
+};
+
+struct SegmentPlan {
+    PlanParams pp;
+    std::vector<PPass> passes;
+    std::vector<uint8_t> blob;         // packed KPass | KStage | KOp | coefficients
+    size_t off_stage = 0, off_op = 0, off_coef = 0;
+    uint64_t n_gates = 0;
+    double flops_per_amp = 0;          // summed over passes
+    uint64_t hash = 0;                 // content + parameters
+    void *dev = nullptr;               // device copy of blob
+    size_t dev_bytes = 0;
+};
+
+// Plan a segment.  `ops` are the lowered gates of the segment's levels in
+// canonical order (level by level; inside a level by lowest qubit).
+SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp);
+
+// Hash of a segment's content and the parameters that shape its plan.
+uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp);
+
+// LDS slot of tile index l under the swizzle of width `swz`.
+uint32_t lds_phys(uint32_t l, int swz);
+
+// Check that every table of the plan is a bijection onto the tile and that
+// every op sits inside its stage and pass; returns "" or a description.
+std::string validate_plan(const SegmentPlan &sp);
+
+// JSON description of a plan (passes, stages, ops, fused unitaries).
+std::string plan_json(const SegmentPlan &sp, bool with_matrices);
+
+}  // namespace qtask

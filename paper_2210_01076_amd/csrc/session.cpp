@@ -1,0 +1,651 @@
+// Session: full and incremental state update on one device.
+//
+// The circuit is cut into segments of K levels.  Each segment has its own
+// plan (a pure function of the segment's gates), and the state after each
+// segment boundary can be kept on the device as a checkpoint (the paper keeps
+// per-net state vectors for the same purpose, Section III-F).  An update
+// after circuit modifiers restores the newest valid checkpoint at or before
+// the first modified level and re-runs the segments from there; when the set
+// of blocks the modifiers can reach is closed under every replayed gate, only
+// the tiles holding those blocks are re-run and only those blocks are stored
+// (the paper's frontier-and-reachability update, Section III-E).  Because
+// plans, kernels and the tile arithmetic do not depend on which tiles run,
+// the incremental result is bitwise identical to a full re-simulation.
+#include "session.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+
+#include "device.h"
+
+namespace qtask {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+#define HIPCHK(expr)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            last_error = std::string(#expr) + ": " + hipGetErrorString(e_); \
+            return QTASK_E_DEVICE;                                          \
+        }                                                                   \
+    } while (0)
+
+Session::Session(int n_, int dtype_, const qtask_opts &o)
+    : circ(n_), n(n_), n_int(std::max(n_, QK_MIN_TILE_BITS)), dtype(dtype_), elem(dtype_ == QTASK_C128 ? 16 : 8),
+      opts(o), plan_only(o.device == QTASK_DEVICE_NONE) {
+    last.struct_size = sizeof(qtask_stats);
+}
+
+Session::~Session() {
+    if (plan_only) return;
+    (void)hipSetDevice(opts.device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &sp : plans_) dfree(sp.dev);
+    dfree(state_.p);
+    for (auto &c : ckpt_) dfree(c.p);
+    dfree(d_partials_);
+    dfree(d_scalars_);
+    dfree(d_u64_);
+    dfree(d_mask_);
+    dfree(d_tiles_);
+    if (ev0_) (void)hipEventDestroy(ev0_);
+    if (ev1_) (void)hipEventDestroy(ev1_);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void *Session::dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (opts.alloc) return opts.alloc(bytes, opts.alloc_ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void Session::dfree(void *p) {
+    if (!p) return;
+    if (opts.free) opts.free(p, opts.alloc_ctx);
+    else (void)hipFree(p);
+}
+
+int Session::init_device() {
+    if (plan_only || dev_ready_) return QTASK_OK;
+    HIPCHK(hipSetDevice(opts.device));
+    if (opts.stream) {
+        stream = static_cast<hipStream_t>(opts.stream);
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        own_stream = true;
+    }
+    HIPCHK(hipEventCreate(&ev0_));
+    HIPCHK(hipEventCreate(&ev1_));
+    dev_ready_ = true;
+    return QTASK_OK;
+}
+
+bool Session::stores_ckpt(size_t j, size_t S) const {
+    if (j == 0 || j >= S) return false;
+    if (opts.max_ckpts < 0) return true;
+    if (opts.max_ckpts == 0) return false;
+    const size_t nb = S - 1;
+    const size_t stride = (nb + size_t(opts.max_ckpts) - 1) / size_t(opts.max_ckpts);
+    return j % std::max<size_t>(stride, 1) == 0;
+}
+
+uint64_t Session::planned_bytes() const {
+    const size_t S = num_segments();
+    uint64_t b = state_bytes();
+    for (size_t j = 1; j < S; ++j)
+        if (stores_ckpt(j, S)) b += state_bytes();
+    return b + (uint64_t(1) << 20);
+}
+
+uint64_t Session::device_bytes() const {
+    uint64_t b = state_.bytes;
+    for (const auto &c : ckpt_) b += c.bytes;
+    for (const auto &sp : plans_) b += sp.dev_bytes;
+    return b;
+}
+
+std::vector<LGate> Session::segment_ops(size_t s) const {
+    std::vector<LGate> ops;
+    const size_t lo = s * size_t(K());
+    const size_t hi = std::min(circ.num_levels(), lo + size_t(K()));
+    for (size_t li = lo; li < hi; ++li) {
+        const Level &lv = circ.level_by_index(li);
+        std::vector<const Gate *> gs;
+        for (uint64_t gid : lv.gates) gs.push_back(&circ.gate(gid));
+        // canonical order inside a level: by lowest qubit (the gates of a
+        // level act on disjoint qubits, so this is a total order)
+        std::sort(gs.begin(), gs.end(), [](const Gate *a, const Gate *b) {
+            const int la = *std::min_element(a->q, a->q + a->nq);
+            const int lb = *std::min_element(b->q, b->q + b->nq);
+            return la < lb;
+        });
+        for (const Gate *g : gs) ops.push_back(lower_gate(g->kind, g->q, g->p, g->id));
+    }
+    return ops;
+}
+
+int Session::ensure_state() {
+    if (state_.p) return QTASK_OK;
+    state_.p = dalloc(state_bytes());
+    if (!state_.p) return QTASK_E_NOMEM;
+    state_.bytes = state_bytes();
+    return QTASK_OK;
+}
+
+int Session::ensure_ckpt(size_t j) {
+    if (ckpt_.size() <= j) {
+        ckpt_.resize(j + 1);
+        ckpt_valid_.resize(j + 1, 0);
+    }
+    if (ckpt_[j].p) return QTASK_OK;
+    ckpt_[j].p = dalloc(state_bytes());
+    if (!ckpt_[j].p) return QTASK_E_NOMEM;
+    ckpt_[j].bytes = state_bytes();
+    ckpt_valid_[j] = 0;
+    return QTASK_OK;
+}
+
+int Session::upload_plan(SegmentPlan &sp) {
+    if (plan_only) return QTASK_OK;
+    sp.dev = dalloc(sp.blob.size());
+    if (!sp.dev) return QTASK_E_NOMEM;
+    sp.dev_bytes = sp.blob.size();
+    HIPCHK(hipMemcpyAsync(sp.dev, sp.blob.data(), sp.blob.size(), hipMemcpyHostToDevice, stream));
+    return QTASK_OK;
+}
+
+namespace {
+
+bool same_gate(const LGate &a, const LGate &b) {
+    if (a.kop != b.kop || a.nq != b.nq) return false;
+    for (int j = 0; j < a.nq; ++j)
+        if (a.q[j] != b.q[j]) return false;
+    return a.m.size() == b.m.size() && std::memcmp(a.m.data(), b.m.data(), a.m.size() * sizeof(cd)) == 0;
+}
+
+bool same_pass(const PPass &a, const PPass &b) {
+    if (a.qlist != b.qlist || a.stages.size() != b.stages.size()) return false;
+    for (size_t i = 0; i < a.stages.size(); ++i) {
+        const PStage &x = a.stages[i], &y = b.stages[i];
+        if (x.tbits != y.tbits || x.mfma != y.mfma || x.ops.size() != y.ops.size()) return false;
+        if (x.U.size() != y.U.size() ||
+            (!x.U.empty() && std::memcmp(x.U.data(), y.U.data(), x.U.size() * sizeof(cd)) != 0))
+            return false;
+        for (size_t k = 0; k < x.ops.size(); ++k)
+            if (!same_gate(x.ops[k], y.ops[k])) return false;
+    }
+    return true;
+}
+
+template <typename F>
+void for_pass_ops(const PPass &p, F &&f) {
+    for (const auto &st : p.stages)
+        for (const auto &g : st.ops) f(g);
+}
+
+uint64_t pext_tile(uint64_t x, const uint8_t *pos, uint32_t npos) {
+    uint64_t t = 0;
+    for (uint32_t k = 0; k < npos; ++k) t |= ((x >> pos[k]) & 1) << k;
+    return t;
+}
+
+}  // namespace
+
+// Decide whether the replay can be restricted to a closed block set; fills S.
+int Session::try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan> &old_plans, BlockSet &S) {
+    const int beta = std::min(opts.block_bits, n_int);
+    const uint64_t nblocks = uint64_t(1) << (n_int - beta);
+    if (nblocks > (uint64_t(1) << 22)) return QTASK_E_UNSUPPORTED;
+    const size_t nseg = plans_.size();
+    if (s_edit >= nseg || s_edit >= old_plans.size()) return QTASK_E_UNSUPPORTED;
+    // every other segment from s0 on must be unchanged
+    for (size_t s = s0; s < nseg; ++s) {
+        if (s == s_edit) continue;
+        if (s >= old_plans.size() || old_plans[s].hash != plans_[s].hash) return QTASK_E_UNSUPPORTED;
+    }
+    if (old_plans[s_edit].hash == plans_[s_edit].hash) {
+        S = BlockSet(nblocks);  // the edits cancelled out: nothing to redo
+        return QTASK_OK;
+    }
+    const auto &op = old_plans[s_edit].passes;
+    const auto &np = plans_[s_edit].passes;
+    size_t pre = 0;
+    while (pre < op.size() && pre < np.size() && same_pass(op[pre], np[pre])) ++pre;
+    size_t suf = 0;
+    while (suf < op.size() - pre && suf < np.size() - pre &&
+           same_pass(op[op.size() - 1 - suf], np[np.size() - 1 - suf]))
+        ++suf;
+    BlockSet d(nblocks);
+    for (size_t i = pre; i < op.size() - suf; ++i)
+        for_pass_ops(op[i], [&](const LGate &g) { add_touched(block_action(g, beta), d); });
+    for (size_t i = pre; i < np.size() - suf; ++i)
+        for_pass_ops(np[i], [&](const LGate &g) { add_touched(block_action(g, beta), d); });
+    bool saturated = d.all();
+    auto prop = [&](const PPass &p) {
+        if (saturated) return;
+        for_pass_ops(p, [&](const LGate &g) { propagate(block_action(g, beta), d); });
+        saturated = d.all();
+    };
+    for (size_t i = np.size() - suf; i < np.size(); ++i) prop(np[i]);
+    for (size_t s = s_edit + 1; s < nseg; ++s)
+        for (const auto &p : plans_[s].passes) prop(p);
+    if (saturated) return QTASK_E_UNSUPPORTED;
+    // closedness over every replayed gate
+    for (size_t s = s0; s < nseg; ++s)
+        for (const auto &p : plans_[s].passes) {
+            bool ok = true;
+            for_pass_ops(p, [&](const LGate &g) {
+                if (ok && !closed_under(block_action(g, beta), d)) ok = false;
+            });
+            if (!ok) return QTASK_E_UNSUPPORTED;
+        }
+    S = d;
+    return QTASK_OK;
+}
+
+int Session::prepare(bool force_full) {
+    const double t0 = now_ms();
+    prep_t0_ = t0;
+    launches.clear();
+    qtask_stats st{};
+    st.struct_size = sizeof(st);
+    const size_t D = circ.num_levels();
+    const size_t S = num_segments();
+    st.levels_total = D;
+    st.total_blocks = uint64_t(1) << (n_int - std::min(opts.block_bits, n_int));
+    prep_S_ = S;
+    prep_mode_ = 0;
+    prep_tiles_.clear();
+
+    PlanParams pp;
+    pp.n = n_int;
+    pp.b = std::min(opts.tile_bits, n_int);
+    pp.c = std::min(opts.low_bits, pp.b);
+    pp.dtype = dtype;
+    pp.fusion = opts.fusion;
+    pp.fuse_k = opts.fuse_width;
+    pp.swz = dtype == QTASK_C128 ? 4 : 5;
+
+    const bool full = force_full || !have_result_;
+    size_t s0 = 0, s_edit = 0;
+    if (!full) {
+        if (!circ.edited()) {
+            st.plan_ms = now_ms() - t0;
+            last = st;
+            return QTASK_OK;  // mode 0: nothing to do
+        }
+        const size_t L = circ.first_edited();
+        s_edit = L / size_t(K());
+        const size_t jmax = std::min(s_edit, S ? S - 1 : 0);
+        for (size_t j = jmax; j >= 1; --j)
+            if (stores_ckpt(j, S) && j < ckpt_valid_.size() && ckpt_valid_[j] && (plan_only || ckpt_[j].p)) {
+                s0 = j;
+                break;
+            }
+    }
+    // (re)plan segments s0..S-1; keep the replaced plans for the tracker
+    std::vector<SegmentPlan> old_plans;
+    if (plans_.size() > S) {
+        for (size_t s = S; s < plans_.size(); ++s) dfree(plans_[s].dev);
+    }
+    old_plans.resize(std::max(plans_.size(), S));
+    for (size_t s = s0; s < plans_.size(); ++s) old_plans[s].hash = plans_[s].hash;
+    plans_.resize(S);
+    for (size_t s = s0; s < S; ++s) {
+        std::vector<LGate> ops = segment_ops(s);
+        const uint64_t h = segment_hash(ops, pp);
+        if (plans_[s].hash == h && (plan_only || plans_[s].dev)) {
+            old_plans[s].hash = h;
+            continue;
+        }
+        SegmentPlan np;
+        try {
+            np = plan_segment(ops, pp);
+        } catch (const std::exception &e) {
+            last_error = e.what();
+            return QTASK_E_ARG;
+        }
+        int rc = upload_plan(np);
+        if (rc != QTASK_OK) return rc;
+        dfree(plans_[s].dev);
+        plans_[s].dev = nullptr;
+        old_plans[s] = std::move(plans_[s]);
+        plans_[s] = std::move(np);
+    }
+    // memory
+    if (!plan_only) {
+        int rc = ensure_state();
+        if (rc != QTASK_OK) return rc;
+        for (size_t j = 1; j < S; ++j)
+            if (stores_ckpt(j, S)) {
+                rc = ensure_ckpt(j);
+                if (rc != QTASK_OK) return rc;
+            }
+        for (size_t j = 0; j < ckpt_.size(); ++j)
+            if (!stores_ckpt(j, S) && ckpt_[j].p) {
+                dfree(ckpt_[j].p);
+                ckpt_[j] = DevBuf{};
+                ckpt_valid_[j] = 0;
+            }
+        if (scalars_cap_ < 2 * (S + 1)) {
+            const size_t cap = 2 * (S + 64);
+            double *p = static_cast<double *>(dalloc(cap * sizeof(double)));
+            if (!p) return QTASK_E_NOMEM;
+            if (d_scalars_) {
+                // keep the norms/scales of still-valid checkpoints
+                HIPCHK(hipMemcpyAsync(p, d_scalars_, scalars_cap_ / 2 * sizeof(double), hipMemcpyDeviceToDevice, stream));
+                HIPCHK(hipMemcpyAsync(p + cap / 2, d_scalars_ + scalars_cap_ / 2, scalars_cap_ / 2 * sizeof(double),
+                                      hipMemcpyDeviceToDevice, stream));
+                HIPCHK(hipStreamSynchronize(stream));
+                dfree(d_scalars_);
+            }
+            d_scalars_ = p;
+            scalars_cap_ = cap;
+        }
+        const uint64_t max_tiles = uint64_t(1) << (n_int - pp.b);
+        const size_t need = std::max<size_t>(max_tiles, 4096);
+        if (partials_cap_ < need) {
+            dfree(d_partials_);
+            d_partials_ = static_cast<double *>(dalloc(need * sizeof(double)));
+            if (!d_partials_) { partials_cap_ = 0; return QTASK_E_NOMEM; }
+            partials_cap_ = need;
+        }
+        if (!d_u64_) {
+            d_u64_ = static_cast<unsigned long long *>(dalloc(4096 * sizeof(unsigned long long)));
+            if (!d_u64_) return QTASK_E_NOMEM;
+            u64_cap_ = 4096;
+        }
+    }
+    const bool renorm = dtype == QTASK_C64 && opts.renorm != 0;
+    prep_renorm_ = renorm;
+    int mode = full ? 1 : 2;
+    BlockSet set;
+    if (!full && opts.closed_mode && !renorm && S > 0) {
+        if (try_closed(s0, s_edit, old_plans, set) == QTASK_OK) mode = 3;
+    }
+    prep_mode_ = mode;
+    prep_s0_ = s0;
+    st.mode = mode;
+    st.first_level = s0 * size_t(K());
+    st.segments_replayed = S - s0;
+    st.levels_replayed = D - std::min(D, st.first_level);
+    st.dirty_blocks = mode == 3 ? set.count() : st.total_blocks;
+    if (mode == 3) prep_set_ = set;
+
+    // tile lists for the closed replay
+    std::vector<size_t> list_off;
+    if (mode == 3) {
+        const int beta = std::min(opts.block_bits, n_int);
+        const std::vector<uint32_t> blocks = set.list();
+        for (size_t s = s0; s < S; ++s)
+            for (size_t p = 0; p < plans_[s].passes.size(); ++p) {
+                const PPass &ps = plans_[s].passes[p];
+                const KPass &kp = reinterpret_cast<const KPass *>(plans_[s].blob.data())[p];
+                uint64_t nonq_low = 0;
+                for (int q = 0; q < beta; ++q)
+                    if (!((ps.qmask >> q) & 1)) nonq_low |= uint64_t(1) << q;
+                std::vector<uint32_t> lows;
+                // every combination of the non-pass bits below beta
+                for (uint64_t sub = nonq_low;; sub = (sub - 1) & nonq_low) {
+                    lows.push_back(uint32_t(sub));
+                    if (sub == 0) break;
+                }
+                std::vector<uint32_t> tl;
+                tl.reserve(blocks.size() * lows.size());
+                for (uint32_t blk : blocks)
+                    for (uint32_t lo : lows)
+                        tl.push_back(uint32_t(pext_tile((uint64_t(blk) << beta) | lo, kp.nonq_pos, kp.n_nonq)));
+                std::sort(tl.begin(), tl.end());
+                tl.erase(std::unique(tl.begin(), tl.end()), tl.end());
+                list_off.push_back(prep_tiles_.size());
+                prep_tiles_.insert(prep_tiles_.end(), tl.begin(), tl.end());
+            }
+        list_off.push_back(prep_tiles_.size());
+        if (!plan_only) {
+            if (tiles_cap_ < prep_tiles_.size()) {
+                dfree(d_tiles_);
+                const size_t cap = prep_tiles_.size() + 4096;
+                d_tiles_ = static_cast<uint32_t *>(dalloc(cap * sizeof(uint32_t)));
+                if (!d_tiles_) { tiles_cap_ = 0; return QTASK_E_NOMEM; }
+                tiles_cap_ = cap;
+            }
+            const auto &w = set.words();
+            if (mask_cap_ < w.size()) {
+                dfree(d_mask_);
+                d_mask_ = static_cast<uint64_t *>(dalloc(w.size() * sizeof(uint64_t)));
+                if (!d_mask_) { mask_cap_ = 0; return QTASK_E_NOMEM; }
+                mask_cap_ = w.size();
+            }
+            if (!prep_tiles_.empty())
+                HIPCHK(hipMemcpyAsync(d_tiles_, prep_tiles_.data(), prep_tiles_.size() * sizeof(uint32_t),
+                                      hipMemcpyHostToDevice, stream));
+            HIPCHK(hipMemcpyAsync(d_mask_, w.data(), w.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream));
+            // pageable copies: make sure they completed before the host vectors change
+            HIPCHK(hipStreamSynchronize(stream));
+        }
+    }
+
+    // launch list
+    size_t li = 0;
+    double bytes = 0, flops = 0;
+    for (size_t s = s0; s < S; ++s) {
+        const SegmentPlan &sp = plans_[s];
+        const int b = sp.pp.b;
+        const uint64_t full_tiles = uint64_t(1) << (n_int - b);
+        const char *blob = static_cast<const char *>(sp.dev);
+        const size_t P = sp.passes.size();
+        for (size_t p = 0; p < P; ++p, ++li) {
+            Launch L{};
+            KArgs &a = L.args;
+            a.dst = state_.p;
+            if (s == s0 && p == 0) {
+                if (s0 == 0) { a.src_basis = 1; a.src = nullptr; }
+                else a.src = plan_only ? nullptr : ckpt_[s0].p;
+            } else {
+                a.src = state_.p;
+            }
+            const bool lastp = p + 1 == P;
+            a.scale = (renorm && p == 0 && s > 0 && !plan_only) ? d_scalars_ + scalars_cap_ / 2 + s : nullptr;
+            a.ckpt = (lastp && s + 1 < S && stores_ckpt(s + 1, S) && !plan_only) ? ckpt_[s + 1].p : nullptr;
+            a.partials = (lastp && renorm) ? d_partials_ : nullptr;
+            a.pass = reinterpret_cast<const KPass *>(blob) + p;
+            a.stages = reinterpret_cast<const KStage *>(blob + sp.off_stage);
+            a.ops = reinterpret_cast<const KOp *>(blob + sp.off_op);
+            a.coefs = blob + sp.off_coef;
+            a.block_bits = uint32_t(std::min(opts.block_bits, n_int));
+            uint64_t tiles = full_tiles;
+            if (mode == 3) {
+                tiles = list_off[li + 1] - list_off[li];
+                a.tile_list = d_tiles_ ? d_tiles_ + list_off[li] : nullptr;
+                a.store_mask = d_mask_;
+            }
+            L.n_tiles = uint32_t(tiles);
+            L.b = b;
+            L.after = (lastp && renorm) ? 1 : 0;
+            L.seg = int(s);
+            if (tiles > 0 || L.after) launches.push_back(L);
+            const double tb = double(uint64_t(1) << b) * double(elem);
+            bytes += double(tiles) * tb * ((a.src_basis ? 0 : 1) + 1 + (a.ckpt ? 1 : 0));
+            double pf = 0;
+            for (const auto &stg : sp.passes[p].stages) pf += stg.flops;
+            flops += double(tiles) * double(uint64_t(1) << b) * pf;
+            st.passes += 1;
+            st.tiles += tiles;
+            st.stages += sp.passes[p].stages.size();
+        }
+        st.gate_amp_updates += sp.n_gates * (uint64_t(1) << n);
+    }
+    if (renorm && S > 0) bytes += 2.0 * double(state_bytes());
+    st.bytes = bytes;
+    st.flops = flops;
+    st.plan_ms = now_ms() - t0;
+    last = st;
+    return QTASK_OK;
+}
+
+int Session::enqueue_after(const Launch &L, hipStream_t s) {
+    if (L.after == 1) {
+        double *norms = d_scalars_;
+        double *scales = d_scalars_ + scalars_cap_ / 2;
+        HIPCHK(launch_sum_partials(d_partials_, L.n_tiles, norms + L.seg + 1, scales + L.seg + 1, s));
+    }
+    return QTASK_OK;
+}
+
+int Session::enqueue_final(hipStream_t s) {
+    if (prep_S_ == 0) {
+        HIPCHK(launch_fill_basis(dtype, state_.p, uint64_t(1) << n_int, s));
+    } else if (prep_renorm_ && prep_mode_ != 0) {
+        HIPCHK(launch_scale(dtype, state_.p, uint64_t(1) << n_int, d_scalars_ + scalars_cap_ / 2 + prep_S_, s));
+    }
+    return QTASK_OK;
+}
+
+int Session::enqueue_prepared(hipStream_t s) {
+    for (const Launch &L : launches) {
+        if (L.n_tiles > 0) HIPCHK(launch_pass(dtype, L.args, L.n_tiles, L.b, s));
+        int rc = enqueue_after(L, s);
+        if (rc != QTASK_OK) return rc;
+    }
+    return enqueue_final(s);
+}
+
+int Session::finish_prepared_host() {
+    if (prep_mode_ == 0) return QTASK_OK;
+    const size_t S = prep_S_;
+    if (ckpt_valid_.size() < S) ckpt_valid_.resize(S, 0);
+    for (size_t j = 0; j < ckpt_valid_.size(); ++j) {
+        if (j >= S || !stores_ckpt(j, S)) ckpt_valid_[j] = 0;
+        else if (j > prep_s0_) ckpt_valid_[j] = 1;
+        // j <= s0: unchanged (valid if it was)
+    }
+    circ.clear_edits();
+    have_result_ = true;
+    state_valid_ = !plan_only;
+    return QTASK_OK;
+}
+
+int Session::update(bool force_full) {
+    const double t0 = now_ms();
+    int rc = init_device();
+    if (rc != QTASK_OK) return rc;
+    rc = prepare(force_full);
+    if (rc != QTASK_OK) {
+        state_valid_ = false;
+        have_result_ = false;
+        return rc;
+    }
+    if (prep_mode_ == 0) {
+        last.wall_ms = now_ms() - t0;
+        return QTASK_OK;
+    }
+    if (!plan_only) {
+        auto fail = [&](int code) {
+            state_valid_ = false;
+            have_result_ = false;
+            for (auto &v : ckpt_valid_) v = 0;
+            return code;
+        };
+        if (hipEventRecord(ev0_, stream) != hipSuccess) return fail(QTASK_E_DEVICE);
+        rc = enqueue_prepared(stream);
+        if (rc != QTASK_OK) {
+            (void)hipStreamSynchronize(stream);
+            return fail(rc);
+        }
+        if (hipEventRecord(ev1_, stream) != hipSuccess) return fail(QTASK_E_DEVICE);
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            last_error = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+            return fail(QTASK_E_DEVICE);
+        }
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) {
+            last.kernel_ms = ms;
+            last.pass_kernel_ms = ms;
+        }
+    }
+    finish_prepared_host();
+    last.wall_ms = now_ms() - t0;
+    return QTASK_OK;
+}
+
+int Session::read(uint64_t first, uint64_t count, void *out) {
+    if (plan_only) return QTASK_E_UNSUPPORTED;
+    if (!state_valid_ || circ.edited()) return QTASK_E_STALE;
+    const uint64_t N = uint64_t(1) << n;
+    if (first > N || count > N - first) return QTASK_E_NOTFOUND;
+    if (count == 0) return QTASK_OK;
+    if (!out) return QTASK_E_ARG;
+    HIPCHK(hipSetDevice(opts.device));
+    HIPCHK(hipMemcpyAsync(out, static_cast<char *>(state_.p) + first * elem, count * elem, hipMemcpyDeviceToHost,
+                          stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return QTASK_OK;
+}
+
+int Session::norm(double *out) {
+    if (plan_only) return QTASK_E_UNSUPPORTED;
+    if (!state_valid_ || circ.edited()) return QTASK_E_STALE;
+    HIPCHK(hipSetDevice(opts.device));
+    const uint64_t N = uint64_t(1) << n_int;
+    HIPCHK(launch_norm(dtype, state_.p, N, d_partials_, reinterpret_cast<double *>(d_u64_), nullptr, stream));
+    double v = 0;
+    HIPCHK(hipMemcpyAsync(&v, d_u64_, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *out = v;
+    return QTASK_OK;
+}
+
+int Session::hash(uint64_t *out) {
+    if (plan_only) return QTASK_E_UNSUPPORTED;
+    if (!state_valid_ || circ.edited()) return QTASK_E_STALE;
+    HIPCHK(hipSetDevice(opts.device));
+    const uint64_t N = uint64_t(1) << n_int;
+    HIPCHK(launch_hash(dtype, state_.p, N, d_u64_ + 1, d_u64_, stream));
+    unsigned long long v = 0;
+    HIPCHK(hipMemcpyAsync(&v, d_u64_, sizeof(v), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *out = v;
+    return QTASK_OK;
+}
+
+int Session::dump(const char *path) {
+    std::ostringstream o;
+    o << "{\"n\":" << n << ",\"n_buffer\":" << n_int << ",\"dtype\":" << dtype << ",\"levels\":" << circ.num_levels()
+      << ",\"gates\":" << circ.num_gates() << ",\"tile_bits\":" << opts.tile_bits << ",\"low_bits\":" << opts.low_bits
+      << ",\"block_bits\":" << std::min(opts.block_bits, n_int) << ",\"ckpt_interval\":" << opts.ckpt_interval
+      << ",\"last\":{\"mode\":" << last.mode << ",\"first_level\":" << last.first_level
+      << ",\"segments_replayed\":" << last.segments_replayed << ",\"passes\":" << last.passes
+      << ",\"tiles\":" << last.tiles << ",\"dirty_blocks\":" << last.dirty_blocks
+      << ",\"total_blocks\":" << last.total_blocks << "}";
+    o << ",\"dirty_block_list\":[";
+    if (last.mode == 3) {
+        const auto l = prep_set_.list();
+        for (size_t i = 0; i < l.size() && i < 65536; ++i) o << (i ? "," : "") << l[i];
+    }
+    o << "],\"segments\":[";
+    for (size_t s = 0; s < plans_.size(); ++s) {
+        if (s) o << ",";
+        o << plan_json(plans_[s], true);
+    }
+    o << "]}";
+    FILE *f = std::fopen(path, "w");
+    if (!f) return QTASK_E_ARG;
+    const std::string js = o.str();
+    const size_t wr = std::fwrite(js.data(), 1, js.size(), f);
+    std::fclose(f);
+    return wr == js.size() ? QTASK_OK : QTASK_E_ARG;
+}
+
+}  // namespace qtask

@@ -1,0 +1,113 @@
+// One simulation handle: circuit store, segment plans, device state and
+// checkpoints, and the full / incremental update.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/qtask.h"
+#include "circuit.h"
+#include "kdefs.h"
+#include "planner.h"
+#include "tracker.h"
+
+namespace qtask {
+
+double now_ms();
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+class Session {
+public:
+    Session(int n, int dtype, const qtask_opts &opts);
+    ~Session();
+
+    Circuit circ;
+    int n;          // user qubits
+    int n_int;      // qubits of the buffer (>= QK_MIN_TILE_BITS)
+    int dtype;
+    size_t elem;    // bytes per amplitude
+    qtask_opts opts;
+    bool plan_only;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    int init_device();   // called lazily; creates stream, scratch
+    int update(bool force_full);
+    int read(uint64_t first, uint64_t count, void *out);
+    int norm(double *out);
+    int hash(uint64_t *out);
+    int dump(const char *path);
+    uint64_t device_bytes() const;
+    uint64_t state_bytes() const { return (uint64_t(1) << n_int) * elem; }
+    // bytes this session needs resident for its current circuit (state,
+    // checkpoints, plans); used for admission
+    uint64_t planned_bytes() const;
+
+    // --- used by the server's batched small-session path
+    int prepare(bool force_full);           // plan + decide the replay (no launches)
+    struct Launch {                          // one pass launch of the prepared replay
+        KArgs args;
+        uint32_t n_tiles;
+        int b;
+        int after;          // 0 none, 1 sum partials -> renorm scale of `seg+1`
+        int seg;
+    };
+    std::vector<Launch> launches;            // filled by prepare()
+    int finish_prepared_host();             // bookkeeping after the launches ran
+    int enqueue_prepared(hipStream_t s);     // launch everything prepare() built
+    int enqueue_after(const Launch &l, hipStream_t s);  // the tail work of a launch (renorm sums)
+    int enqueue_final(hipStream_t s);        // work after the last pass (final renorm, empty circuit)
+
+    void *state() const { return state_.p; }
+    bool state_valid() const { return state_valid_; }
+    qtask_stats last{};
+    std::string last_error;
+
+    void *dalloc(size_t bytes);
+    void dfree(void *p);
+
+private:
+    int K() const { return opts.ckpt_interval; }
+    size_t num_segments() const { return (circ.num_levels() + size_t(K()) - 1) / size_t(K()); }
+    bool stores_ckpt(size_t j, size_t S) const;
+    std::vector<LGate> segment_ops(size_t s) const;
+    int ensure_state();
+    int ensure_ckpt(size_t j);
+    int upload_plan(SegmentPlan &sp);
+    int try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan> &old_plans, BlockSet &S);
+    int build_tile_lists(const BlockSet &S, size_t s0);
+
+    DevBuf state_;
+    std::vector<DevBuf> ckpt_;            // index j = boundary j (state after j*K levels)
+    std::vector<uint8_t> ckpt_valid_;
+    std::vector<SegmentPlan> plans_;
+    bool state_valid_ = false;
+    bool have_result_ = false;
+
+    // device scratch
+    double *d_partials_ = nullptr;  size_t partials_cap_ = 0;
+    double *d_scalars_ = nullptr;   size_t scalars_cap_ = 0;  // norms[j], scales[j] per boundary
+    unsigned long long *d_u64_ = nullptr;  size_t u64_cap_ = 0;
+    uint64_t *d_mask_ = nullptr;    size_t mask_cap_ = 0;
+    uint32_t *d_tiles_ = nullptr;   size_t tiles_cap_ = 0;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    bool dev_ready_ = false;
+
+    // prepared replay
+    size_t prep_s0_ = 0, prep_S_ = 0;
+    int prep_mode_ = 0;
+    bool prep_renorm_ = false;
+    BlockSet prep_set_;
+    std::vector<uint32_t> prep_tiles_;
+    double prep_t0_ = 0;
+    friend struct SessionAccess;
+};
+
+}  // namespace qtask

@@ -1,0 +1,136 @@
+#include "tracker.h"
+
+#include <algorithm>
+
+namespace qtask {
+
+void BlockSet::reset(uint64_t nblocks, bool full) {
+    n_ = nblocks;
+    w_.assign((nblocks + 63) / 64, full ? ~uint64_t(0) : 0);
+    if (full && (nblocks & 63)) w_.back() = (uint64_t(1) << (nblocks & 63)) - 1;
+}
+
+uint64_t BlockSet::count() const {
+    uint64_t c = 0;
+    for (uint64_t x : w_) c += uint64_t(__builtin_popcountll(x));
+    return c;
+}
+
+void BlockSet::merge(const BlockSet &o) {
+    for (size_t i = 0; i < w_.size(); ++i) w_[i] |= o.w_[i];
+}
+
+std::vector<uint32_t> BlockSet::list() const {
+    std::vector<uint32_t> out;
+    for (size_t i = 0; i < w_.size(); ++i) {
+        uint64_t x = w_[i];
+        while (x) {
+            const int b = __builtin_ctzll(x);
+            out.push_back(uint32_t(i * 64 + b));
+            x &= x - 1;
+        }
+    }
+    return out;
+}
+
+BlockAction block_action(const LGate &g, int beta) {
+    BlockAction a;
+    const int k = g.nq, dim = 1 << k;
+    // local bit of gate qubit j is (k-1-j); split local index into high part
+    // (qubits >= beta, in hmask order) and low part
+    std::vector<int> hi_j;  // gate qubit indices j with q >= beta, ascending by qubit
+    for (int j = 0; j < k; ++j)
+        if (g.q[j] >= beta) hi_j.push_back(j);
+    std::sort(hi_j.begin(), hi_j.end(), [&](int x, int y) { return g.q[x] < g.q[y]; });
+    a.nh = int(hi_j.size());
+    for (int j : hi_j) {
+        a.hmask |= uint64_t(1) << (g.q[j] - beta);
+        a.hq.push_back(g.q[j] - beta);
+    }
+    const int hd = 1 << a.nh;
+    auto hpart = [&](int local) {
+        int h = 0;
+        for (int i = 0; i < a.nh; ++i) h |= ((local >> (k - 1 - hi_j[i])) & 1) << i;
+        return h;
+    };
+    a.touched.assign(hd, 0);
+    a.couple.assign(size_t(hd) * hd, 0);
+    for (int r = 0; r < dim; ++r) {
+        bool identity_row = true;
+        for (int c = 0; c < dim; ++c) {
+            const cd v = g.m[size_t(r) * dim + c];
+            if (v != (r == c ? cd(1, 0) : cd(0, 0))) identity_row = false;
+            if (v != cd(0, 0) && hpart(r) != hpart(c)) {
+                a.couple[size_t(hpart(r)) * hd + hpart(c)] = 1;
+                a.any_couple = true;
+            }
+        }
+        if (!identity_row) {
+            a.touched[hpart(r)] = 1;
+            a.any_touch = true;
+        }
+    }
+    return a;
+}
+
+namespace {
+// Visit every group of 2^nh blocks that differ only in the gate's high bits:
+// f(blocks[2^nh]) with blocks[h] the block index whose high part is h.
+template <typename F>
+void for_groups(const BlockAction &a, uint64_t nblocks, F &&f) {
+    const int hd = 1 << a.nh;
+    uint64_t idx[8];
+    for (uint64_t base = 0; base < nblocks; ++base) {
+        if (base & a.hmask) continue;
+        for (int h = 0; h < hd; ++h) {
+            uint64_t j = base;
+            for (int i = 0; i < a.nh; ++i)
+                if ((h >> i) & 1) j |= uint64_t(1) << a.hq[i];
+            idx[h] = j;
+        }
+        if (!f(idx)) return;
+    }
+}
+}  // namespace
+
+void add_touched(const BlockAction &a, BlockSet &out) {
+    if (!a.any_touch) return;
+    const int hd = 1 << a.nh;
+    for_groups(a, out.size(), [&](const uint64_t *idx) {
+        for (int h = 0; h < hd; ++h)
+            if (a.touched[h]) out.set(idx[h]);
+        return true;
+    });
+}
+
+void propagate(const BlockAction &a, BlockSet &d) {
+    if (!a.any_couple) return;
+    const int hd = 1 << a.nh;
+    for_groups(a, d.size(), [&](const uint64_t *idx) {
+        bool in[8];
+        for (int h = 0; h < hd; ++h) in[h] = d.test(idx[h]);
+        for (int ho = 0; ho < hd; ++ho)
+            for (int hi = 0; hi < hd; ++hi)
+                if (a.couple[size_t(ho) * hd + hi] && in[hi]) d.set(idx[ho]);
+        return true;
+    });
+}
+
+bool closed_under(const BlockAction &a, const BlockSet &s) {
+    if (!a.any_couple) return true;
+    const int hd = 1 << a.nh;
+    bool ok = true;
+    for_groups(a, s.size(), [&](const uint64_t *idx) {
+        for (int ho = 0; ho < hd && ok; ++ho)
+            for (int hi = 0; hi < hd; ++hi)
+                if ((a.couple[size_t(ho) * hd + hi] || a.couple[size_t(hi) * hd + ho]) &&
+                    s.test(idx[ho]) != s.test(idx[hi])) {
+                    ok = false;
+                    break;
+                }
+        return ok;
+    });
+    return ok;
+}
+
+}  // namespace qtask

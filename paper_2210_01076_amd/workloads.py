@@ -70,8 +70,9 @@ def _gate(rng: np.random.Generator, kind: str, qubits: Sequence[int]) -> Gate:
 def dense_random_circuit(n: int, levels: int, seed: int,
                          kinds: Sequence[str] = CFG1_KINDS) -> List[Net]:
     """Every qubit gets one gate per net.  Qubits are visited in a seeded
-    random order; a drawn two-qubit kind also takes the next unvisited qubit
-    (as its target); when only one qubit is left a one-qubit kind is drawn."""
+    random order; a drawn multi-qubit kind also takes the next unvisited
+    qubits (control first); when too few qubits are left a one-qubit kind is
+    drawn instead."""
     rng = np.random.default_rng(seed)
     one = [k for k in kinds if N_QUBITS[k] == 1]
     nets: List[Net] = []
@@ -81,14 +82,11 @@ def dense_random_circuit(n: int, levels: int, seed: int,
         i = 0
         while i < n:
             kind = str(kinds[int(rng.integers(len(kinds)))])
-            if N_QUBITS[kind] == 2 and i + 1 >= n:
+            if i + N_QUBITS[kind] > n:
                 kind = str(one[int(rng.integers(len(one)))])
-            if N_QUBITS[kind] == 2:
-                net.append(_gate(rng, kind, (order[i], order[i + 1])))
-                i += 2
-            else:
-                net.append(_gate(rng, kind, (order[i],)))
-                i += 1
+            k = N_QUBITS[kind]
+            net.append(_gate(rng, kind, order[i:i + k]))
+            i += k
         nets.append(net)
     return nets
 

@@ -1,0 +1,266 @@
+"""Host-side logic of the library, run without a GPU: the C ABI's exports and
+error semantics, the planner (checked by emulating its dumped plans on the
+CPU against the oracle) and the affected-block tracker (the paper's worked
+example, and soundness against oracle snapshots).  Sessions here are
+plan-only (device QTASK_DEVICE_NONE): no device memory, no kernels."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2210_01076_amd import qtask as Q
+from paper_2210_01076_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def plan_only(n, dtype="c128", **kw):
+    return Q.Simulator(n, dtype, device=Q.QTASK_DEVICE_NONE, **kw)
+
+
+# ------------------------------------------------------------------- ABI
+
+def test_library_exports_every_declared_symbol():
+    lib = Q.load()
+    with open(os.path.join(ROOT, "include", "qtask.h")) as f:
+        header = f.read()
+    names = set(re.findall(r"^\s*(?:const\s+char\s*\*|int)\s*(qtask_\w+)\s*\(", header, re.M))
+    assert len(names) >= 30
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+        assert name in Q._SIGS, name
+
+
+def test_status_strings_and_version():
+    lib = Q.load()
+    for code in range(9):
+        assert lib.qtask_status_string(code)
+    import ctypes
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert lib.qtask_version(ctypes.byref(a), ctypes.byref(b)) == 0 and a.value >= 1
+
+
+def test_create_argument_errors():
+    lib = Q.load()
+    import ctypes
+    h = ctypes.c_void_p()
+    o = Q.qtask_opts_default(device=Q.QTASK_DEVICE_NONE)
+    assert lib.qtask_create(0, 0, ctypes.byref(o), ctypes.byref(h)) == Q.QTASK_E_ARG
+    assert lib.qtask_create(35, 0, ctypes.byref(o), ctypes.byref(h)) == Q.QTASK_E_ARG
+    assert lib.qtask_create(5, 7, ctypes.byref(o), ctypes.byref(h)) == Q.QTASK_E_ARG
+    bad = Q.qtask_opts_default(device=Q.QTASK_DEVICE_NONE, tile_bits=20)
+    assert lib.qtask_create(5, 0, ctypes.byref(bad), ctypes.byref(h)) == Q.QTASK_E_ARG
+    bad = Q.qtask_opts_default(device=Q.QTASK_DEVICE_NONE, ckpt_interval=-3)
+    assert lib.qtask_create(5, 0, ctypes.byref(bad), ctypes.byref(h)) == Q.QTASK_E_ARG
+    assert lib.qtask_create(5, 0, ctypes.byref(o), None) == Q.QTASK_E_ARG
+
+
+def test_circuit_store_errors_keep_state():
+    with plan_only(5) as sim:
+        sim.build([[("h", (0,), ())], [("cx", (4, 3), ())]])
+        lib = Q.load()
+        import ctypes
+        n_before = ctypes.c_uint64()
+        lib.qtask_num_gates(sim.h, ctypes.byref(n_before))
+        with pytest.raises(Q.QtaskError) as e:          # shares q4 with the CX: paper's conflict
+            Q.qtask_insert_gate(sim.h, sim.levels[1], "cx", (4, 1))
+        assert e.value.code == Q.QTASK_E_CONFLICT
+        for qs, ps, kind in [((5,), (), "h"), ((1, 1), (), "cx"), ((0,), (), "rx"), ((0,), (1.0, 2.0), "rz"),
+                             ((-1,), (), "x"), ((0,), (float("nan"),), "ry")]:
+            with pytest.raises(Q.QtaskError) as e:
+                Q.qtask_insert_gate(sim.h, sim.levels[0], kind, qs, ps)
+            assert e.value.code == Q.QTASK_E_ARG, (kind, qs, ps)
+        with pytest.raises(Q.QtaskError) as e:
+            Q.qtask_remove_gate(sim.h, 999999)
+        assert e.value.code == Q.QTASK_E_NOTFOUND
+        with pytest.raises(Q.QtaskError) as e:
+            Q.qtask_insert_gate(sim.h, 424242, "h", (1,))
+        assert e.value.code == Q.QTASK_E_NOTFOUND
+        n_after = ctypes.c_uint64()
+        lib.qtask_num_gates(sim.h, ctypes.byref(n_after))
+        assert n_after.value == n_before.value == 2
+        # reads are unsupported on a plan-only session
+        with pytest.raises(Q.QtaskError) as e:
+            sim.state()
+        assert e.value.code in (Q.QTASK_E_UNSUPPORTED, Q.QTASK_E_STALE)
+
+
+def test_level_ids_are_stable():
+    with plan_only(4) as sim:
+        a = sim.add_level()
+        b = sim.add_level()
+        c = sim.add_level(1)            # between a and b
+        assert [Q.qtask_level_at(sim.h, i) for i in range(3)] == [a, c, b]
+        Q.qtask_remove_level(sim.h, c)
+        assert [Q.qtask_level_at(sim.h, i) for i in range(2)] == [a, b]
+        with pytest.raises(Q.QtaskError):
+            Q.qtask_remove_level(sim.h, c)
+
+
+# ----------------------------------------------------------- plan emulation
+
+def _apply_local(psi, n, qs, m):
+    """Apply matrix m (first-listed qubit = high local bit) on qubits qs."""
+    k = len(qs)
+    t = psi.reshape([2] * n)  # axis a <-> qubit n-1-a
+    axes = [n - 1 - q for q in qs]
+    t = np.moveaxis(t, axes, range(k))
+    shp = t.shape
+    t = (m @ t.reshape(1 << k, -1)).reshape(shp)
+    return np.moveaxis(t, range(k), axes).reshape(-1)
+
+
+def emulate(dump, n):
+    """Run the dumped plan of every segment on the CPU in complex128."""
+    psi = oracle.basis(n).astype(np.complex128)
+    for seg in dump["segments"]:
+        assert seg["check"] == "", seg["check"]
+        for ps in seg["passes"]:
+            for st in ps["stages"]:
+                if st["dense"]:
+                    qs = st["qubits"]
+                    U = np.array([complex(a, b) for a, b in st["U"]]).reshape(1 << len(qs), 1 << len(qs))
+                    # register convention: bit j of the index <-> qs[j]; as a
+                    # local matrix the first-listed qubit is the high bit
+                    psi = _apply_local(psi, n, list(reversed(qs)), U)
+                else:
+                    for op in st["ops"]:
+                        m = np.array([complex(a, b) for a, b in op["m"]])
+                        d = int(round(np.sqrt(m.size)))
+                        psi = _apply_local(psi, n, op["q"], m.reshape(d, d))
+    return psi
+
+
+@pytest.mark.parametrize("n,b,c,seed,fam", [
+    (5, 4, 2, 1, "dense"), (6, 5, 3, 2, "dense"), (8, 6, 4, 3, "layered"), (9, 6, 3, 4, "dense"),
+    (10, 7, 4, 5, "layered"), (10, 10, 4, 6, "dense"), (7, 4, 0, 7, "ladder")])
+def test_planner_emulation_matches_oracle(n, b, c, seed, fam):
+    if fam == "dense":
+        nets = W.dense_random_circuit(n, 12, seed, kinds=W.GATE_KINDS)
+    elif fam == "layered":
+        nets = W.layered_circuit(n, 6, seed)
+    else:
+        nets = W.cp_ladder_circuit(n, 5, seed)
+    with plan_only(n, tile_bits=b, low_bits=c, ckpt_interval=7) as sim:
+        sim.build(nets)
+        sim.update()
+        dump = sim.dump()
+    got = emulate(dump, n)
+    want = oracle.simulate(n, nets)
+    np.testing.assert_allclose(got, want, atol=1e-12)
+    # every source gate lands in exactly one pass
+    assert sum(seg["gates"] for seg in dump["segments"]) == W.count_gates(nets)
+
+
+def test_planner_auto_fusion_makes_dense_stages():
+    # deep circuit on 4 qubits: every stage is long enough to fuse
+    rng = np.random.default_rng(11)
+    nets = []
+    for _ in range(40):
+        nets.append([("ry", (q,), (float(rng.uniform(0, 6)),)) for q in range(4)])
+        nets.append([("cx", (0, 1), ()), ("cx", (2, 3), ())])
+        nets.append([("cz", (1, 2), ())])
+    with plan_only(4, tile_bits=4, low_bits=0, ckpt_interval=1000) as sim:
+        sim.build(nets)
+        sim.update()
+        dump = sim.dump()
+    dense = [st for seg in dump["segments"] for p in seg["passes"] for st in p["stages"] if st["dense"]]
+    assert dense, "expected fused dense stages"
+    np.testing.assert_allclose(emulate(dump, 4), oracle.simulate(4, nets), atol=1e-12)
+
+
+# ------------------------------------------------------------------ tracker
+
+def _worked():
+    with open(os.path.join(GOLDEN, "worked_example.json")) as f:
+        gold = json.load(f)
+    nets = [[(g[0], tuple(g[1]), ()) for g in net] for net in gold["nets"]]
+    return gold, nets
+
+
+def test_worked_example_dirty_blocks():
+    gold, nets = _worked()
+    with plan_only(gold["n"], block_bits=gold["block_bits"], ckpt_interval=1) as sim:
+        sim.build(nets)
+        st = sim.update()
+        assert st["mode"] == 1
+        i, j = gold["gate_names"]["G8"]
+        sim.apply_edit(W.Edit("remove", i, pos=j))
+        sim.apply_edit(W.Edit("insert", i, (gold["g10"][0], tuple(gold["g10"][1]), ())))
+        st = sim.update()
+        assert st["mode"] == 3
+        assert st["dirty_blocks"] == len(gold["dirty_blocks_after_edits"])
+        dump = sim.dump()
+        assert dump["dirty_block_list"] == gold["dirty_blocks_after_edits"]
+        # updated amplitudes = the paper's 24
+        bb = gold["block_bits"]
+        amps = [a for blk in dump["dirty_block_list"] for a in range(blk << bb, (blk + 1) << bb)]
+        assert len(amps) == gold["updated_amplitude_count"]
+        # replay starts at the checkpoint right before the edited net
+        assert st["first_level"] == i
+
+
+def test_worked_example_without_checkpoints_replays_everything():
+    gold, nets = _worked()
+    with plan_only(gold["n"], block_bits=gold["block_bits"], ckpt_interval=1, max_ckpts=0) as sim:
+        sim.build(nets)
+        sim.update()
+        i, j = gold["gate_names"]["G8"]
+        sim.apply_edit(W.Edit("remove", i, pos=j))
+        st = sim.update()
+        # the Hadamard net couples every block, so without a checkpoint after
+        # it the affected set is not closed and the whole state is redone
+        assert st["mode"] == 2 and st["first_level"] == 0
+
+
+def test_cancelling_edits_redo_nothing():
+    gold, nets = _worked()
+    with plan_only(gold["n"], block_bits=2, ckpt_interval=1) as sim:
+        sim.build(nets)
+        sim.update()
+        sim.apply_edit(W.Edit("remove", 3, pos=0))
+        sim.apply_edit(W.Edit("insert", 3, nets[3][0]))
+        st = sim.update()
+        assert st["mode"] == 3 and st["dirty_blocks"] == 0 and st["tiles"] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tracker_sound_against_oracle(seed):
+    """Blocks whose amplitudes actually change (at every checkpoint boundary
+    and at the end) lie inside the tracker's affected set."""
+    rng = np.random.default_rng(seed)
+    n, bb, K = 7, 3, 2
+    kinds = ("x", "cx", "ccx", "swap", "z", "s", "t", "cz", "cp", "h", "rx")
+    nets = W.dense_random_circuit(n, 10, 50 + seed, kinds=("x", "cx", "z", "s", "cz", "swap", "t"))
+    with plan_only(n, block_bits=bb, ckpt_interval=K, tile_bits=5, low_bits=2) as sim:
+        sim.build(nets)
+        sim.update()
+        for trial in range(4):
+            old = [list(x) for x in nets]
+            li = int(rng.integers(len(nets)))
+            if nets[li] and rng.random() < 0.5:
+                e = W.Edit("remove", li, pos=int(rng.integers(len(nets[li]))))
+            else:
+                free = [q for q in range(n) if all(q not in g[1] for g in nets[li])]
+                kind = kinds[int(rng.integers(len(kinds)))]
+                k = W.N_QUBITS[kind]
+                if len(free) < k:
+                    continue
+                qs = tuple(int(q) for q in rng.choice(free, size=k, replace=False))
+                e = W.Edit("insert", li, (kind, qs, tuple(rng.uniform(0, 6, W.N_PARAMS[kind]))))
+            W.apply_edit(nets, e)
+            sim.apply_edit(e)
+            st = sim.update()
+            a = oracle.snapshots(n, old)
+            b = oracle.snapshots(n, nets)
+            if st["mode"] == 3:
+                dirty = set(sim.dump()["dirty_block_list"])
+                for lv in range(len(nets) + 1):
+                    if lv % K == 0 or lv == len(nets):
+                        assert oracle.changed_blocks(a[lv], b[lv], bb) <= dirty, (trial, lv)
+            else:
+                assert st["mode"] == 2
