@@ -570,16 +570,12 @@ __global__ void qk_copy_blocks(void *dst_, const void *src_, const uint32_t *blo
 
 // ---------------------------------------------------------------- launchers
 namespace {
-template <typename R>
-void set_lds_limit() {
-    static bool done = false;
-    if (!done) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&qk_pass<R>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&qk_pass_batch<R>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        done = true;
-    }
+// Workgroups above 64 KiB of dynamic LDS need an explicit opt-in per kernel.
+hipError_t allow_lds(const void *fn, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
 }
 
 uint32_t fill_grid(uint64_t n) {
@@ -591,15 +587,18 @@ uint32_t fill_grid(uint64_t n) {
 
 hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
     const uint32_t threads = 1u << (b - QK_G);
+    (void)hipGetLastError();  // start from a clean error state
     if (dtype == 0) {
-        set_lds_limit<double>();
         const size_t lds = (size_t(1) << b) * sizeof(double2);
+        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<double>), lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(qk_pass<double>, dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
                            a.stages, a.ops, static_cast<const double *>(a.coefs), a.tile_list, a.store_mask,
                            a.scale, a.partials, a.src_basis, a.block_bits);
     } else {
-        set_lds_limit<float>();
         const size_t lds = (size_t(1) << b) * sizeof(float2);
+        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<float>), lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(qk_pass<float>, dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
                            a.stages, a.ops, static_cast<const float *>(a.coefs), a.tile_list, a.store_mask,
                            a.scale, a.partials, a.src_basis, a.block_bits);
@@ -609,11 +608,14 @@ hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipSt
 
 hipError_t launch_pass_batch(int dtype, const KBatchItem *items, uint32_t n_items, uint32_t n_groups,
                              uint32_t max_threads, uint32_t lds_bytes, hipStream_t s) {
+    (void)hipGetLastError();
     if (dtype == 0) {
-        set_lds_limit<double>();
+        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<double>), lds_bytes);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(qk_pass_batch<double>, dim3(n_groups), dim3(max_threads), lds_bytes, s, items, n_items);
     } else {
-        set_lds_limit<float>();
+        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<float>), lds_bytes);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(qk_pass_batch<float>, dim3(n_groups), dim3(max_threads), lds_bytes, s, items, n_items);
     }
     return hipGetLastError();

@@ -75,22 +75,49 @@ def test_remove_then_reinsert_restores_bits():
         assert bytes_equal(before, s.state())
 
 
-def test_closed_mode_on_permutation_circuit():
-    """Mostly-classical circuit: the affected set stays closed, so only its
-    tiles are re-run; the result still equals a full re-simulation."""
-    n = 16
-    kinds = ("x", "cx", "ccx", "swap", "z", "s", "t", "cz")
-    nets = [[("h", (q,), ()) for q in range(4)]] + W.dense_random_circuit(n, 30, 8, kinds=kinds)
+def _arith_net(rng, n, low):
+    """Controlled gates whose targets lie below the block bits (controls
+    anywhere) plus diagonal gates: nothing moves amplitude between blocks."""
+    net, used = [], set()
+    for _ in range(6):
+        kind = ("ccx", "cx", "cz", "cp", "t")[int(rng.integers(5))]
+        if kind in ("ccx", "cx"):
+            k = 3 if kind == "ccx" else 2
+            tgt = int(rng.integers(low))
+            ctl = [int(q) for q in rng.choice(n, size=k - 1, replace=False)]
+            qs = tuple(ctl) + (tgt,)
+        elif kind in ("cz", "cp"):
+            qs = tuple(int(q) for q in rng.choice(n, size=2, replace=False))
+        else:
+            qs = (int(rng.integers(n)),)
+        if len(set(qs)) < len(qs) or used & set(qs):
+            continue
+        used |= set(qs)
+        net.append((kind, qs, (float(rng.uniform(0, 6)),) if kind == "cp" else ()))
+    return net
+
+
+def test_closed_mode_on_arithmetic_circuit():
+    """Arithmetic-style circuit: the affected set stays closed, so only its
+    tiles are re-run; the result still equals a full re-simulation and the
+    oracle."""
+    n, beta = 16, 8
     rng = np.random.default_rng(3)
+    nets = [[("h", (q,), ()) for q in range(n)]] + [_arith_net(rng, n, beta) for _ in range(30)]
     modes = []
-    with sim(n, nets, block_bits=8, ckpt_interval=4) as s:
+    with sim(n, nets, block_bits=beta, ckpt_interval=4) as s:
         s.update()
         for trial in range(10):
-            li = int(rng.integers(len(nets) - 10, len(nets)))
-            if nets[li]:
+            li = int(rng.integers(len(nets) - 12, len(nets)))
+            if nets[li] and trial % 2 == 0:
                 e = W.Edit("remove", li, pos=int(rng.integers(len(nets[li]))))
             else:
-                e = W.Edit("insert", li, ("x", (int(rng.integers(n)),), ()))
+                free = [q for q in range(n) if all(q not in g[1] for g in nets[li])]
+                hi = [q for q in free if q >= beta]
+                lo = [q for q in free if q < beta]
+                if len(hi) < 2 or not lo:
+                    continue
+                e = W.Edit("insert", li, ("ccx", (hi[0], hi[1], lo[0]), ()))
             W.apply_edit(nets, e)
             s.apply_edit(e)
             s.update()
