@@ -138,6 +138,8 @@ def main():
     from paper_2210_01076_amd import qtask as Q
     from paper_2210_01076_amd import workloads as W
 
+    copy_gbs = Q.qtask_copy_bandwidth(0, 1 << 30, 20)
+    log("copy kernel ceiling %.1f GB/s" % copy_gbs)
     wl = W.config(2)
     sim128, nets, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup)
     r64 = None
@@ -177,6 +179,8 @@ def main():
                                "CNOT matching), 100 batches of 1-4 random gate inserts/removals; complex128",
                    "qubits": 24, "levels": 200, "batches": 100, "ckpt_levels": 50},
         "frac_of_peak": round(r128["full_gbs"] / HBM_PEAK_GBS, 4),
+        "copy_ceiling_gbs": round(copy_gbs, 1),
+        "frac_of_copy_ceiling": round(r128["full_gbs"] / copy_gbs, 4),
         "full_ms_p50": r128["full_ms_p50"],
         "incremental_ms_p50": r128["inc_ms_p50"],
         "incremental_ms_p99": r128["inc_ms_p99"],

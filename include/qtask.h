@@ -125,6 +125,7 @@ typedef struct qtask_stats {
     uint64_t gate_amp_updates; /* sum over replayed gates of 2^n */
     double bytes;              /* algorithmic HBM bytes of the launched kernels */
     double flops;              /* algorithmic flops of the launched kernels */
+    double mfma_flops;         /* the part of `flops` done by dense fused unitaries on the matrix cores */
     double kernel_ms;          /* device time from the first to the last launched kernel */
     double pass_kernel_ms;     /* device time of the pass kernels alone */
     double plan_ms;            /* host planning time */
@@ -200,6 +201,13 @@ int qtask_get_opts(qtask_t h, qtask_opts *out);
 /* Write the current plan (passes, stages, ops, fused unitaries, affected
  * blocks of the last update) as JSON to `path`.  Paper: dump_graph (Table II). */
 int qtask_dump_plan(qtask_t h, const char *path);
+
+/* ----------------------------------------------------------- diagnostics */
+/* Bandwidth of a plain device copy kernel: copies `bytes` (rounded down to
+ * 256 B) between two fresh device buffers `iters` times and returns the
+ * achieved (read + write) GB/s.  This is the measured ceiling the pass
+ * kernels are compared against. */
+int qtask_copy_bandwidth(int device, uint64_t bytes, int iters, double *gbps);
 
 /* --------------------------------------------------------------- serving */
 /* A server keeps many sessions resident on one device and runs their update

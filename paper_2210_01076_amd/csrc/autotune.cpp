@@ -1,0 +1,127 @@
+// Autotuner for the tile shape (tile bits b, contiguous low bits c).
+//
+// The paper leaves the block size to the user because the best value depends
+// on the circuit and the machine (Section IV-F).  Here the library measures
+// instead: at the first update of a session it plans the circuit's first
+// levels with every candidate shape, runs each plan on the device (twice,
+// keeping the second timing), and keeps the shape with the lowest time per
+// gate.  The pick is cached per (device, state qubits, dtype, fusion, gate
+// mix) and frozen for the session, so every later plan of the session, full
+// or incremental, uses the same shape and results stay bitwise reproducible.
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "device.h"
+#include "session.h"
+
+namespace qtask {
+
+namespace {
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int, int, uint64_t>, std::pair<int, int>> g_cache;
+
+uint64_t mix_signature(const std::vector<LGate> &ops) {
+    // histogram of op classes in tenths of the total
+    uint64_t cnt[16] = {0};
+    for (const auto &g : ops) cnt[g.kop & 15]++;
+    uint64_t sig = 0;
+    for (int k = 0; k < 16; ++k) sig = sig * 11 + (ops.empty() ? 0 : (cnt[k] * 10 + ops.size() / 2) / ops.size());
+    return sig;
+}
+}  // namespace
+
+int Session::autotune() {
+    if (plan_only) return QTASK_OK;
+    int rc = init_device();
+    if (rc != QTASK_OK) return rc;
+    // tuning prefix: the first levels, at most one segment, at most ~600 gates
+    std::vector<LGate> ops;
+    {
+        const size_t D = circ.num_levels();
+        for (size_t li = 0; li < D && li < size_t(K()) && ops.size() < 600; ++li) {
+            const Level &lv = circ.level_by_index(li);
+            for (uint64_t gid : lv.gates) {
+                const Gate &g = circ.gate(gid);
+                ops.push_back(lower_gate(g.kind, g.q, g.p, g.id));
+            }
+        }
+    }
+    if (ops.empty()) return QTASK_OK;
+    const auto key = std::make_tuple(opts.device, n_int, dtype, opts.fusion, opts.fuse_width, mix_signature(ops));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            opts.tile_bits = it->second.first;
+            opts.low_bits = it->second.second;
+            return QTASK_OK;
+        }
+    }
+    rc = ensure_state();
+    if (rc != QTASK_OK) return rc;
+    std::vector<std::pair<int, int>> cand;
+    for (int b : {10, 11, 12, 13})
+        for (int c : {3, 4, 5, 6, 8})
+            if (b <= n_int && c <= b - 3 && (opts.fusion != QTASK_FUSE_DENSE || b - opts.fuse_width >= 4))
+                cand.emplace_back(b, c);
+    if (cand.empty()) cand.emplace_back(std::min(opts.tile_bits, n_int), std::min(opts.low_bits, n_int));
+    double best_t = 1e300;
+    std::pair<int, int> best = cand.front();
+    for (const auto &bc : cand) {
+        PlanParams pp;
+        pp.n = n_int;
+        pp.b = bc.first;
+        pp.c = bc.second;
+        pp.dtype = dtype;
+        pp.fusion = opts.fusion;
+        pp.fuse_k = opts.fuse_width;
+        pp.swz = dtype == QTASK_C128 ? 4 : 5;
+        SegmentPlan sp;
+        try {
+            sp = plan_segment(ops, pp);
+        } catch (const std::exception &e) {
+            continue;
+        }
+        rc = upload_plan(sp);
+        if (rc != QTASK_OK) return rc;
+        float ms = 0;
+        for (int rep = 0; rep < 2 && rc == QTASK_OK; ++rep) {
+            if (hipEventRecord(ev0_, stream) != hipSuccess) rc = QTASK_E_DEVICE;
+            const char *blob = static_cast<const char *>(sp.dev);
+            for (size_t p = 0; p < sp.passes.size() && rc == QTASK_OK; ++p) {
+                KArgs a{};
+                a.dst = state_.p;
+                a.src = p == 0 ? nullptr : state_.p;
+                a.src_basis = p == 0 ? 1 : 0;
+                a.pass = reinterpret_cast<const KPass *>(blob) + p;
+                a.stages = reinterpret_cast<const KStage *>(blob + sp.off_stage);
+                a.ops = reinterpret_cast<const KOp *>(blob + sp.off_op);
+                a.coefs = blob + sp.off_coef;
+                a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
+                if (launch_pass(dtype, a, uint32_t(uint64_t(1) << (n_int - pp.b)), pp.b, stream) != hipSuccess)
+                    rc = QTASK_E_DEVICE;
+            }
+            if (rc == QTASK_OK && (hipEventRecord(ev1_, stream) != hipSuccess ||
+                                   hipStreamSynchronize(stream) != hipSuccess ||
+                                   hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
+                rc = QTASK_E_DEVICE;
+        }
+        dfree(sp.dev);
+        if (rc != QTASK_OK) {
+            last_error = "autotune: device error";
+            return rc;
+        }
+        if (ms < best_t) {
+            best_t = ms;
+            best = bc;
+        }
+    }
+    opts.tile_bits = best.first;
+    opts.low_bits = best.second;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = best;
+    return QTASK_OK;
+}
+
+}  // namespace qtask

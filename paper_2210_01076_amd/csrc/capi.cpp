@@ -2,6 +2,7 @@
 // Every entry point catches C++ exceptions and turns them into status codes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -109,7 +110,7 @@ int qtask_create(int n_qubits, qtask_dtype dtype, const qtask_opts *user, qtask_
             std::memcpy(&o, user, user->struct_size);
             o.struct_size = sizeof(o);
         }
-        if (o.tile_bits == 0) o.tile_bits = dtype == QTASK_C128 ? 12 : 13;
+        if (o.tile_bits == 0) o.tile_bits = dtype == QTASK_C128 ? 11 : 12;
         if (o.low_bits == 0) o.low_bits = dtype == QTASK_C128 ? 4 : 5;
         if (o.block_bits == 0) o.block_bits = 10;
         if (o.fuse_width == 0) o.fuse_width = 4;
@@ -119,7 +120,9 @@ int qtask_create(int n_qubits, qtask_dtype dtype, const qtask_opts *user, qtask_
         if (o.block_bits < 0 || o.block_bits > QK_MAX_QUBITS) return QTASK_E_ARG;
         if (o.fusion < QTASK_FUSE_AUTO || o.fusion > QTASK_FUSE_DENSE) return QTASK_E_ARG;
         if (o.fusion == QTASK_FUSE_DENSE && (o.fuse_width < 4 || o.fuse_width > QK_MAX_DENSE_K)) return QTASK_E_ARG;
-        if (o.fusion == QTASK_FUSE_DENSE) return QTASK_E_UNSUPPORTED;
+        if (o.fusion == QTASK_FUSE_DENSE && o.fuse_width > QK_G &&
+            std::min(o.tile_bits, std::max(n_qubits, QK_MIN_TILE_BITS)) < 10)
+            return QTASK_E_UNSUPPORTED;  // matrix-core stages need tiles of >= 2^10 amplitudes
         if (o.ckpt_interval < 1 || o.max_ckpts < -1) return QTASK_E_ARG;
         if (o.device < QTASK_DEVICE_NONE) return QTASK_E_ARG;
         if ((o.alloc == nullptr) != (o.free == nullptr)) return QTASK_E_ARG;
@@ -332,6 +335,37 @@ int qtask_dump_plan(qtask_t h, const char *path) {
         Session *s = S(h);
         if (!s || !path) return QTASK_E_ARG;
         return s->dump(path);
+    });
+}
+
+int qtask_copy_bandwidth(int device, uint64_t bytes, int iters, double *gbps) {
+    return guarded([&] {
+        if (!gbps || iters < 1 || bytes < 256) return QTASK_E_ARG;
+        if (hipSetDevice(device) != hipSuccess) return QTASK_E_DEVICE;
+        bytes &= ~uint64_t(255);
+        void *a = nullptr, *b = nullptr;
+        if (hipMalloc(&a, bytes) != hipSuccess) { (void)hipGetLastError(); return QTASK_E_NOMEM; }
+        if (hipMalloc(&b, bytes) != hipSuccess) { (void)hipGetLastError(); (void)hipFree(a); return QTASK_E_NOMEM; }
+        int rc = QTASK_OK;
+        hipStream_t s = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float ms = 0;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess || hipMemsetAsync(a, 0, bytes, s) != hipSuccess ||
+            qtask::launch_copy(b, a, bytes / 32, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess)
+            rc = QTASK_E_DEVICE;
+        for (int i = 0; i < iters && rc == QTASK_OK; ++i)
+            if (qtask::launch_copy((i & 1) ? a : b, (i & 1) ? b : a, bytes / 32, s) != hipSuccess) rc = QTASK_E_DEVICE;
+        if (rc == QTASK_OK && (hipEventRecord(e1, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = QTASK_E_DEVICE;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        (void)hipFree(a);
+        (void)hipFree(b);
+        if (rc == QTASK_OK) *gbps = 2.0 * double(bytes) * iters / (double(ms) * 1e-3) / 1e9;
+        return rc;
     });
 }
 

@@ -41,4 +41,7 @@ hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s);
 hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint32_t *blocks, uint32_t n_blocks,
                               int block_bits, hipStream_t s);
 
+// dst = src over n 32-byte words (plain streaming copy)
+hipError_t launch_copy(void *dst, const void *src, uint64_t n32, hipStream_t s);
+
 }  // namespace qtask

@@ -35,7 +35,11 @@ enum KOpType : uint8_t {
     KOP_SWAP = 8,  // exact exchange of bits a and b             coef: none
     KOP_U2 = 9,    // dense 4x4 on (a,b), local 2*bit(a)+bit(b)  coef: 32
     KOP_CCX = 10,  // exact exchange on bit c where a = b = 1    coef: none
-    KOP_DENSE = 11 // dense 16x16 on all QK_G register bits      coef: 512
+    KOP_DENSE = 11,// dense 16x16 on all QK_G register bits      coef: 512
+    KOP_UR = 12,   // real 2x2 on bit a (H, RY)                 coef: m00 m01 m10 m11 (4 reals)
+    KOP_UX = 13,   // [[a, ib], [ic, d]] with a,b,c,d real (RX)  coef: a b c d (4)
+    KOP_P1 = 14,   // diag(1, p) on bit a (Z, S, T, ...)         coef: p (2)
+    KOP_P2 = 15    // diag(1, 1, 1, p) on (a, b) (CZ, CP)        coef: p (2)
 };
 
 enum KStageKind : uint32_t {
@@ -51,6 +55,8 @@ struct KOp {
 struct KStage {
     uint32_t reg_off[QK_NREG];        // LDS slot of register i relative to the thread base
     uint32_t thr_off[QK_MAX_THR_BITS];// LDS slot contribution of thread-index bit k
+    uint64_t g_reg[QK_NREG];          // first/last stage: global offset of register i
+    uint64_t g_thr[QK_MAX_THR_BITS];  // first/last stage: global offset of thread-index bit k
     uint32_t op_begin, op_count;
     uint32_t kind;                    // KStageKind
     uint32_t k;                       // MFMA stage: qubits of the dense unitary
@@ -60,16 +66,16 @@ struct KStage {
     uint32_t col_off[QK_MAX_TILE_BITS];    // MFMA stage: LDS slot contribution of column bit
 };
 
+// A pass: its first stage loads its registers straight from global memory and
+// its last stage stores straight from registers (both through their own
+// global maps, chosen so that consecutive lanes touch consecutive
+// addresses); the stages in between exchange data through LDS.
 struct KPass {
-    uint64_t g_i[QK_NREG];              // global offset of load register i
-    uint64_t g_thr[QK_MAX_THR_BITS];    // global offset contribution of thread bit k
-    uint32_t p_i[QK_NREG];              // LDS slot of load register i
-    uint32_t p_thr[QK_MAX_THR_BITS];    // LDS slot contribution of thread bit k
     uint8_t nonq_pos[QK_MAX_QUBITS];    // global bit of tile-index bit k
     uint8_t pad[2];
     uint32_t n_nonq;                    // n - b
     uint32_t n_thr;                     // b - QK_G
-    uint32_t stage_begin, stage_count;
+    uint32_t stage_begin, stage_count;  // stage_count >= 1
 };
 
 // Launch arguments of one pass (passed by value).
@@ -87,6 +93,8 @@ struct KArgs {
     double *partials;          // optional: per-tile sum |a|^2 in FP64 (indexed by blockIdx)
     uint32_t src_basis;        // 1: the input is |0...0> (src unused)
     uint32_t block_bits;       // store_mask granularity
+    uint32_t has_mfma;         // the pass has matrix-core stages
+    uint32_t pad0;
 };
 
 // Work item of the batched small-session launch.

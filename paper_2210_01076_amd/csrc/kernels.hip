@@ -183,6 +183,61 @@ __device__ __forceinline__ void op_dense(R (&re)[NR], R (&im)[NR], const R *__re
     }
 }
 
+template <int A, typename R>
+__device__ __forceinline__ void op_ur(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R m00 = c[0], m01 = c[1], m10 = c[2], m11 = c[3];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & (1 << A)) continue;
+        const int j = i | (1 << A);
+        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
+        re[i] = m00 * xr + m01 * yr;
+        im[i] = m00 * xi + m01 * yi;
+        re[j] = m10 * xr + m11 * yr;
+        im[j] = m10 * xi + m11 * yi;
+    }
+}
+
+// [[a, i b], [i c, d]], a b c d real
+template <int A, typename R>
+__device__ __forceinline__ void op_ux(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R a = c[0], b = c[1], cc = c[2], d = c[3];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i & (1 << A)) continue;
+        const int j = i | (1 << A);
+        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
+        re[i] = a * xr - b * yi;
+        im[i] = a * xi + b * yr;
+        re[j] = d * yr - cc * xi;
+        im[j] = d * yi + cc * xr;
+    }
+}
+
+template <int A, typename R>
+__device__ __forceinline__ void op_p1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R pr = c[0], pi = c[1];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (!(i & (1 << A))) continue;
+        const R xr = re[i], xi = im[i];
+        re[i] = pr * xr - pi * xi;
+        im[i] = pr * xi + pi * xr;
+    }
+}
+
+template <int A, int B, typename R>
+__device__ __forceinline__ void op_p2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+    const R pr = c[0], pi = c[1];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (!(i & (1 << A)) || !(i & (1 << B))) continue;
+        const R xr = re[i], xi = im[i];
+        re[i] = pr * xr - pi * xi;
+        im[i] = pr * xi + pi * xr;
+    }
+}
+
 #define SW1(F)                                   \
     switch (op.a) {                              \
     case 0: F<0>(re, im, c); break;              \
@@ -240,11 +295,25 @@ __device__ __forceinline__ void apply_op(const KOp op, R (&re)[NR], R (&im)[NR],
     case KOP_U2: SW2(op_u2) break;
     case KOP_CCX: SW3(op_ccx) break;
     case KOP_DENSE: op_dense(re, im, c); break;
+    case KOP_UR: SW1(op_ur) break;
+    case KOP_UX: SW1(op_ux) break;
+    case KOP_P1: SW1(op_p1) break;
+    case KOP_P2: SW2(op_p2) break;
     default: break;
     }
 }
 
-// ---------------------------------------------------- deterministic reduce
+// ----------------------------------------------------- barriers, reduce
+// Workgroup barrier that orders LDS only.  The pass kernels never read global
+// memory written by another thread of the same launch, so the barrier does
+// not need to drain outstanding global loads (which would cancel the
+// prefetch of the next tile).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum over the workgroup in a fixed order: a butterfly inside each wave,
 // then wave results added in wave order by thread 0.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -257,7 +326,7 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) scratch[wave] = v;
-    __syncthreads();
+    lds_barrier();
     double s = 0;
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
@@ -266,8 +335,137 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
     return s;  // valid in thread 0
 }
 
-// -------------------------------------------------------------- pass body
+// ------------------------------------------------------------- pass body
 template <typename R>
+__device__ __forceinline__ void run_ops(const KStage *__restrict__ S, const KOp *__restrict__ ops,
+                                        const R *__restrict__ coefs, R (&re)[NR], R (&im)[NR]) {
+    const uint32_t oe = S->op_begin + S->op_count;
+    for (uint32_t oi = S->op_begin; oi < oe; ++oi) {
+        const KOp op = ops[oi];
+        apply_op<R>(op, re, im, coefs + op.coef);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ uint32_t thr_lds(const KStage *__restrict__ S, uint32_t n_thr, uint32_t t) {
+    uint32_t o = 0;
+    for (uint32_t k = 0; k < n_thr; ++k)
+        if ((t >> k) & 1u) o ^= S->thr_off[k];
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ uint64_t thr_glb(const KStage *__restrict__ S, uint32_t n_thr, uint32_t t) {
+    uint64_t o = 0;
+    for (uint32_t k = 0; k < n_thr; ++k)
+        if ((t >> k) & 1u) o |= S->g_thr[k];
+    return o;
+}
+
+// ------------------------------------------------------------ MFMA stage
+// Y = U X for one dense 2^K x 2^K complex unitary on the stage's K tile bits,
+// over all 2^(b-K) columns of the tile held in LDS.  The complex product is
+// done as the real block product [Yr; Yi] = [[Ur, -Ui], [Ui, Ur]] [Xr; Xi]
+// (no 3-multiplication trick, so rounding matches a plain complex product)
+// with 16x16x4 MFMA tiles: each wave owns 2^(6-K) column blocks of 16 columns
+// and all 2^(K-3) row blocks, reads its columns, accumulates, then writes the
+// same columns back (waves never touch each other's columns).
+template <typename R> struct MfmaT;
+template <> struct MfmaT<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // output register i of lane l holds row 4*i + l/16 of the 16x16 block
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+template <> struct MfmaT<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // output register i of lane l holds row 4*(l/16) + i of the 16x16 block
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+template <typename R, int K>
+__device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const R *__restrict__ coefs,
+                                             R *__restrict__ lr) {
+    using M = MfmaT<R>;
+    constexpr int DIM = 1 << K;     // complex dimension
+    constexpr int MR = 2 * DIM;     // real rows = real inner dimension
+    constexpr int RB = MR / 16;     // row blocks
+    constexpr int KS = MR / 4;      // inner steps of 4
+    constexpr int CB = 64 / DIM;    // column blocks per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const R *__restrict__ U = coefs + S->coef;
+    const uint32_t ncb = S->n_col_bits;
+    // LDS slot contribution of this lane's and each column block's column bits
+    uint32_t lane_off = 0;
+    for (int j = 0; j < 4; ++j)
+        if ((lane >> j) & 1) lane_off ^= S->col_off[j];
+    uint32_t cb_off[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const uint32_t blk = uint32_t(wave * CB + cb);
+        uint32_t o = 0;
+        for (uint32_t j = 4; j < ncb; ++j)
+            if ((blk >> (j - 4)) & 1) o ^= S->col_off[j];
+        cb_off[cb] = o ^ lane_off;
+    }
+    typename M::acc_t acc[RB][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = typename M::acc_t{0, 0, 0, 0};
+#pragma unroll 2
+    for (int s = 0; s < KS; ++s) {
+        const int kk = 4 * s + (lane >> 4);          // real inner index of this lane
+        const int uk = kk & (DIM - 1);
+        const int part = kk >= DIM ? 1 : 0;          // 0: Xr, 1: Xi
+        const uint32_t roff = S->row_off[uk];
+        R bv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) bv[cb] = lr[2 * (cb_off[cb] ^ roff) + part];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int rr = 16 * rb + (lane & 15);    // real output row of this lane's A value
+            const int ur = rr & (DIM - 1);
+            const R re = U[2 * (ur * DIM + uk)], im = U[2 * (ur * DIM + uk) + 1];
+            const bool top = rr < DIM;
+            const R av = (top == (part == 0)) ? re : (top ? -im : im);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = M::mma(av, bv[cb], acc[rb][cb]);
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = 16 * rb + M::row(lane, i);
+            const uint32_t roff = S->row_off[rr & (DIM - 1)];
+            const int part = rr >= DIM ? 1 : 0;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) lr[2 * (cb_off[cb] ^ roff) + part] = acc[rb][cb][i];
+        }
+}
+
+template <typename R>
+__device__ __forceinline__ void mfma_stage(const KStage *__restrict__ S, const R *__restrict__ coefs,
+                                           typename V2<R>::T *__restrict__ lds) {
+    R *lr = reinterpret_cast<R *>(lds);
+    switch (S->k) {
+    case 4: mfma_stage_k<R, 4>(S, coefs, lr); break;
+    case 5: mfma_stage_k<R, 5>(S, coefs, lr); break;
+    case 6: mfma_stage_k<R, 6>(S, coefs, lr); break;
+    default: break;
+    }
+}
+
+// One tile: the first stage's registers come straight from global memory,
+// the middle stages go through LDS, the last stage's registers go straight
+// back to global memory.
+template <typename R, bool MF>
 __device__ __forceinline__ void pass_body(uint32_t tile, uint32_t part_idx, void *dst_, const void *src_,
                                           void *ckpt_, const KPass *__restrict__ P,
                                           const KStage *__restrict__ stages, const KOp *__restrict__ ops,
@@ -281,90 +479,107 @@ __device__ __forceinline__ void pass_body(uint32_t tile, uint32_t part_idx, void
     const uint32_t n_nonq = P->n_nonq;
     for (uint32_t k = 0; k < n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
     const uint32_t n_thr = P->n_thr;
-    uint64_t gt = base;
-    uint32_t pt = 0;
-    for (uint32_t k = 0; k < n_thr; ++k)
-        if ((t >> k) & 1u) { gt |= P->g_thr[k]; pt ^= P->p_thr[k]; }
+    const uint32_t ns = P->stage_count;
+    const KStage *__restrict__ S0 = stages + P->stage_begin;
+    const KStage *__restrict__ SL = S0 + (ns - 1);
 
-    C v[NR];
-    if (src_basis) {
+    R re[NR], im[NR];
+    {
+        const uint64_t g0 = base | thr_glb<R>(S0, n_thr, t);
+        if (src_basis) {
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const uint64_t idx = gt | P->g_i[i];
-            v[i].x = idx == 0 ? R(1) : R(0);
-            v[i].y = R(0);
-        }
-    } else {
-        const C *src = static_cast<const C *>(src_);
+            for (int i = 0; i < NR; ++i) {
+                re[i] = (g0 | S0->g_reg[i]) == 0 ? R(1) : R(0);
+                im[i] = R(0);
+            }
+        } else {
+            const C *src = static_cast<const C *>(src_);
 #pragma unroll
-        for (int i = 0; i < NR; ++i) v[i] = src[gt | P->g_i[i]];
-        if (scale) {
-            const R sc = R(scale[0]);
+            for (int i = 0; i < NR; ++i) {
+                const C y = src[g0 | S0->g_reg[i]];
+                re[i] = y.x;
+                im[i] = y.y;
+            }
+            if (scale) {
+                const R sc = R(scale[0]);
 #pragma unroll
-            for (int i = 0; i < NR; ++i) { v[i].x *= sc; v[i].y *= sc; }
+                for (int i = 0; i < NR; ++i) { re[i] *= sc; im[i] *= sc; }
+            }
         }
     }
+    run_ops<R>(S0, ops, coefs, re, im);
+    if (ns > 1) {
+        uint32_t bt = thr_lds<R>(S0, n_thr, t);
 #pragma unroll
-    for (int i = 0; i < NR; ++i) lds[pt ^ P->p_i[i]] = v[i];
-    __syncthreads();
-
-    const uint32_t ns = P->stage_count;
-    const KStage *st = stages + P->stage_begin;
-    for (uint32_t si = 0; si < ns; ++si) {
-        const KStage *S = st + si;
-        if (S->kind == KSTAGE_LIST) {
-            uint32_t bt = 0;
-            for (uint32_t k = 0; k < n_thr; ++k)
-                if ((t >> k) & 1u) bt ^= S->thr_off[k];
-            R re[NR], im[NR];
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                const C x = lds[bt ^ S->reg_off[i]];
-                re[i] = x.x;
-                im[i] = x.y;
-            }
-            const uint32_t oe = S->op_begin + S->op_count;
-            for (uint32_t oi = S->op_begin; oi < oe; ++oi) {
-                const KOp op = ops[oi];
-                apply_op<R>(op, re, im, coefs + op.coef);
-            }
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                C x;
-                x.x = re[i];
-                x.y = im[i];
-                lds[bt ^ S->reg_off[i]] = x;
-            }
+        for (int i = 0; i < NR; ++i) {
+            C y;
+            y.x = re[i];
+            y.y = im[i];
+            lds[bt ^ S0->reg_off[i]] = y;
         }
-        __syncthreads();
+        lds_barrier();
+        for (uint32_t si = 1; si + 1 < ns; ++si) {
+            const KStage *__restrict__ S = S0 + si;
+            if (MF && S->kind == KSTAGE_MFMA) {
+                mfma_stage<R>(S, coefs, lds);
+            } else if (S->kind == KSTAGE_LIST) {
+                bt = thr_lds<R>(S, n_thr, t);
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const C y = lds[bt ^ S->reg_off[i]];
+                    re[i] = y.x;
+                    im[i] = y.y;
+                }
+                run_ops<R>(S, ops, coefs, re, im);
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    C y;
+                    y.x = re[i];
+                    y.y = im[i];
+                    lds[bt ^ S->reg_off[i]] = y;
+                }
+            }
+            lds_barrier();
+        }
+        bt = thr_lds<R>(SL, n_thr, t);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const C y = lds[bt ^ SL->reg_off[i]];
+            re[i] = y.x;
+            im[i] = y.y;
+        }
+        run_ops<R>(SL, ops, coefs, re, im);
     }
 
     C *dst = static_cast<C *>(dst_);
     C *ck = static_cast<C *>(ckpt_);
+    const uint64_t gl = base | thr_glb<R>(SL, n_thr, t);
     double acc = 0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const C x = lds[pt ^ P->p_i[i]];
-        const uint64_t idx = gt | P->g_i[i];
+        C y;
+        y.x = re[i];
+        y.y = im[i];
+        const uint64_t idx = gl | SL->g_reg[i];
         bool ok = true;
         if (store_mask) {
             const uint64_t blk = idx >> block_bits;
             ok = (store_mask[blk >> 6] >> (blk & 63)) & 1;
         }
         if (ok) {
-            dst[idx] = x;
-            if (ck) ck[idx] = x;
+            dst[idx] = y;
+            if (ck) ck[idx] = y;
         }
-        if (partials) acc += double(x.x) * double(x.x) + double(x.y) * double(x.y);
+        if (partials) acc += double(y.x) * double(y.x) + double(y.y) * double(y.y);
     }
     if (partials) {
         __shared__ double red[16];
-        const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) partials[part_idx] = s;
+        const double sum = block_sum(acc, red);
+        if (threadIdx.x == 0) partials[part_idx] = sum;
     }
 }
 
-template <typename R>
+template <typename R, bool MF>
 __global__ void __launch_bounds__(512)
 qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, const KStage *__restrict__ stages,
         const KOp *__restrict__ ops, const R *__restrict__ coefs, const uint32_t *__restrict__ tile_list,
@@ -373,8 +588,8 @@ qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, 
     extern __shared__ __align__(16) unsigned char smem[];
     using C = typename V2<R>::T;
     const uint32_t tile = tile_list ? tile_list[blockIdx.x] : blockIdx.x;
-    pass_body<R>(tile, blockIdx.x, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale, partials,
-                 src_basis, block_bits, reinterpret_cast<C *>(smem));
+    pass_body<R, MF>(tile, blockIdx.x, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale, partials,
+                     src_basis, block_bits, reinterpret_cast<C *>(smem));
 }
 
 // Batched pass round over many small sessions that share one tile shape:
@@ -396,8 +611,9 @@ qk_pass_batch(const KBatchItem *__restrict__ items, uint32_t n_items) {
     if (local >= it->n_tiles || it->threads != blockDim.x) return;
     const KArgs &a = it->args;
     const uint32_t tile = a.tile_list ? a.tile_list[local] : local;
-    pass_body<R>(tile, local, a.dst, a.src, a.ckpt, a.pass, a.stages, a.ops, static_cast<const R *>(a.coefs),
-                 a.store_mask, a.scale, a.partials, a.src_basis, a.block_bits, reinterpret_cast<C *>(smem));
+    pass_body<R, false>(tile, local, a.dst, a.src, a.ckpt, a.pass, a.stages, a.ops,
+                        static_cast<const R *>(a.coefs), a.store_mask, a.scale, a.partials, a.src_basis,
+                        a.block_bits, reinterpret_cast<C *>(smem));
 }
 
 // ------------------------------------------------------------- reductions
@@ -568,6 +784,13 @@ __global__ void qk_copy_blocks(void *dst_, const void *src_, const uint32_t *blo
     }
 }
 
+// Plain streaming copy: each thread moves 32-byte words with a grid stride.
+__global__ void __launch_bounds__(256) qk_copy(double4 *__restrict__ dst, const double4 *__restrict__ src,
+                                               uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------- launchers
 namespace {
 // Workgroups above 64 KiB of dynamic LDS need an explicit opt-in per kernel.
@@ -585,25 +808,24 @@ uint32_t fill_grid(uint64_t n) {
 }
 }  // namespace
 
-hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
+template <typename R, bool MF>
+hipError_t launch_pass_t(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
     const uint32_t threads = 1u << (b - QK_G);
-    (void)hipGetLastError();  // start from a clean error state
-    if (dtype == 0) {
-        const size_t lds = (size_t(1) << b) * sizeof(double2);
-        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<double>), lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(qk_pass<double>, dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
-                           a.stages, a.ops, static_cast<const double *>(a.coefs), a.tile_list, a.store_mask,
-                           a.scale, a.partials, a.src_basis, a.block_bits);
-    } else {
-        const size_t lds = (size_t(1) << b) * sizeof(float2);
-        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<float>), lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(qk_pass<float>, dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
-                           a.stages, a.ops, static_cast<const float *>(a.coefs), a.tile_list, a.store_mask,
-                           a.scale, a.partials, a.src_basis, a.block_bits);
-    }
+    const size_t lds = (size_t(1) << b) * sizeof(typename V2<R>::T);
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<R, MF>), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((qk_pass<R, MF>), dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
+                       a.stages, a.ops, static_cast<const R *>(a.coefs), a.tile_list, a.store_mask, a.scale,
+                       a.partials, a.src_basis, a.block_bits);
     return hipGetLastError();
+}
+
+hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
+    (void)hipGetLastError();  // start from a clean error state
+    if (n_tiles == 0) return hipSuccess;
+    if (a.has_mfma)
+        return dtype == 0 ? launch_pass_t<double, true>(a, n_tiles, b, s) : launch_pass_t<float, true>(a, n_tiles, b, s);
+    return dtype == 0 ? launch_pass_t<double, false>(a, n_tiles, b, s) : launch_pass_t<float, false>(a, n_tiles, b, s);
 }
 
 hipError_t launch_pass_batch(int dtype, const KBatchItem *items, uint32_t n_items, uint32_t n_groups,
@@ -698,6 +920,15 @@ hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s) 
         hipLaunchKernelGGL(qk_fill_basis<double>, dim3(fill_grid(n)), dim3(256), 0, s, state, n);
     else
         hipLaunchKernelGGL(qk_fill_basis<float>, dim3(fill_grid(n)), dim3(256), 0, s, state, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t n32, hipStream_t s) {
+    (void)hipGetLastError();
+    uint64_t g = (n32 + 255) / 256;
+    if (g > 256 * 64) g = 256 * 64;
+    hipLaunchKernelGGL(qk_copy, dim3(uint32_t(g < 1 ? 1 : g)), dim3(256), 0, s, static_cast<double4 *>(dst),
+                       static_cast<const double4 *>(src), n32);
     return hipGetLastError();
 }
 

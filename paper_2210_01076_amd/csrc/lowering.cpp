@@ -83,10 +83,14 @@ static void push(std::vector<double> &v, cd z) {
 }
 
 double LGate::flops_per_amp() const {
-    // complex multiply = 6 real flops, complex add = 2
+    // real flops per amplitude as executed (complex multiply = 6 flops,
+    // complex add = 2; a real-by-complex multiply = 2)
     switch (kop) {
     case KOP_U1: return 14;
+    case KOP_UR: case KOP_UX: return 6;
     case KOP_D1: case KOP_A1: return 6;
+    case KOP_P1: return 3;        // half of the amplitudes get a phase
+    case KOP_P2: return 1.5;      // a quarter of the amplitudes get a phase
     case KOP_CU: return 7;        // half of the amplitudes see a 2x2
     case KOP_D2: return 6;
     case KOP_U2: return 30;
@@ -103,11 +107,19 @@ LGate lower_gate(int kind, const int *qubits, const double *params, uint64_t gat
     g.gate_id = gate_id;
     const auto &m = g.m;
     switch (kind) {
-    case QTASK_H: case QTASK_RX: case QTASK_RY:
-        g.kop = KOP_U1;
-        for (int i = 0; i < 4; ++i) push(g.coef, m[i]);
+    case QTASK_H: case QTASK_RY:  // real matrices
+        g.kop = KOP_UR;
+        for (int i = 0; i < 4; ++i) g.coef.push_back(m[i].real());
         break;
-    case QTASK_Z: case QTASK_S: case QTASK_SDG: case QTASK_T: case QTASK_TDG: case QTASK_RZ:
+    case QTASK_RX:  // real diagonal, imaginary off-diagonal
+        g.kop = KOP_UX;
+        g.coef = {m[0].real(), m[1].imag(), m[2].imag(), m[3].real()};
+        break;
+    case QTASK_Z: case QTASK_S: case QTASK_SDG: case QTASK_T: case QTASK_TDG:  // diag(1, p)
+        g.kop = KOP_P1; g.diagonal = g.monomial = true;
+        push(g.coef, m[3]);
+        break;
+    case QTASK_RZ:
         g.kop = KOP_D1; g.diagonal = g.monomial = true;
         push(g.coef, m[0]); push(g.coef, m[3]);
         break;
@@ -121,9 +133,9 @@ LGate lower_gate(int kind, const int *qubits, const double *params, uint64_t gat
     case QTASK_CX:
         g.kop = KOP_CX; g.monomial = true;
         break;
-    case QTASK_CZ: case QTASK_CP:
-        g.kop = KOP_D2; g.diagonal = g.monomial = true;
-        for (int i = 0; i < 4; ++i) push(g.coef, m[size_t(i) * 4 + i]);
+    case QTASK_CZ: case QTASK_CP:  // diag(1, 1, 1, p)
+        g.kop = KOP_P2; g.diagonal = g.monomial = true;
+        push(g.coef, m[15]);
         break;
     case QTASK_SWAP:
         g.kop = KOP_SWAP; g.monomial = true;

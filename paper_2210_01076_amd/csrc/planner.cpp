@@ -60,37 +60,63 @@ std::vector<int> lane_order(const std::vector<int> &bits, int swz) {
 }
 
 bool mergeable(const LGate &g) {
-    return g.nq == 1 && (g.kop == KOP_U1 || g.kop == KOP_D1 || g.kop == KOP_A1);
+    return g.nq == 1 && (g.kop == KOP_U1 || g.kop == KOP_D1 || g.kop == KOP_A1 || g.kop == KOP_UR ||
+                         g.kop == KOP_UX || g.kop == KOP_P1);
 }
 
 void set_1q_coef(LGate &g) {
     g.coef.clear();
     auto push = [&](cd z) { g.coef.push_back(z.real()); g.coef.push_back(z.imag()); };
-    if (g.kop == KOP_D1) { push(g.m[0]); push(g.m[3]); }
-    else if (g.kop == KOP_A1) { push(g.m[1]); push(g.m[2]); }
-    else for (int i = 0; i < 4; ++i) push(g.m[i]);
+    switch (g.kop) {
+    case KOP_D1: push(g.m[0]); push(g.m[3]); break;
+    case KOP_P1: push(g.m[3]); break;
+    case KOP_A1: push(g.m[1]); push(g.m[2]); break;
+    case KOP_UR: for (int i = 0; i < 4; ++i) g.coef.push_back(g.m[i].real()); break;
+    default: for (int i = 0; i < 4; ++i) push(g.m[i]); break;
+    }
 }
 
-// later * earlier for two one-qubit gates on the same qubit
+// later * earlier for two one-qubit gates on the same qubit.  The class of the
+// product follows from the classes of the factors (structural zeros, real
+// entries and unit entries stay exact), never from the values.
 LGate merge_1q(const LGate &later, const LGate &earlier) {
     LGate r = earlier;
     r.gate_id = 0;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             r.m[i * 2 + j] = later.m[i * 2 + 0] * earlier.m[0 * 2 + j] + later.m[i * 2 + 1] * earlier.m[1 * 2 + j];
-    const bool ld = later.kop == KOP_D1, ed = earlier.kop == KOP_D1;
-    const bool la = later.kop == KOP_A1, ea = earlier.kop == KOP_A1;
-    if ((ld && ed) || (la && ea)) {
-        r.kop = KOP_D1; r.diagonal = true; r.monomial = true;
-        r.m[1] = r.m[2] = cd(0, 0);  // structural zeros stay exact
-    } else if ((ld && ea) || (la && ed)) {
+    auto diag = [](uint8_t k) { return k == KOP_D1 || k == KOP_P1; };
+    const uint8_t a = later.kop, b = earlier.kop;
+    if (a == KOP_P1 && b == KOP_P1) {
+        r.kop = KOP_P1; r.diagonal = r.monomial = true;
+        r.m[0] = cd(1, 0); r.m[1] = r.m[2] = cd(0, 0);
+    } else if (diag(a) && diag(b)) {
+        r.kop = KOP_D1; r.diagonal = r.monomial = true;
+        r.m[1] = r.m[2] = cd(0, 0);
+    } else if (a == KOP_A1 && b == KOP_A1) {
+        r.kop = KOP_D1; r.diagonal = r.monomial = true;
+        r.m[1] = r.m[2] = cd(0, 0);
+    } else if ((diag(a) && b == KOP_A1) || (a == KOP_A1 && diag(b))) {
         r.kop = KOP_A1; r.diagonal = false; r.monomial = true;
         r.m[0] = r.m[3] = cd(0, 0);
+    } else if (a == KOP_UR && b == KOP_UR) {
+        r.kop = KOP_UR; r.diagonal = r.monomial = false;
+        for (auto &z : r.m) z = cd(z.real(), 0);
     } else {
-        r.kop = KOP_U1; r.diagonal = false; r.monomial = false;
+        r.kop = KOP_U1; r.diagonal = r.monomial = false;
     }
     set_1q_coef(r);
     return r;
+}
+
+// cost units (register FMAs per amplitude) used to decide merges
+double op_cost(const LGate &g) {
+    switch (g.kop) {
+    case KOP_U1: return 8;
+    case KOP_UR: case KOP_UX: case KOP_D1: case KOP_A1: return 4;
+    case KOP_P1: return 2;
+    default: return 0;
+    }
 }
 
 std::vector<cd> matmul(const std::vector<cd> &a, const std::vector<cd> &b, int dim) {
@@ -152,8 +178,11 @@ struct Packer {
                     const int tb = tile_bit_of(ps, g.q[0]);
                     const int li = last[tb];
                     if (li >= 0 && mergeable(st.ops[li])) {
-                        st.ops[li] = merge_1q(g, st.ops[li]);
-                        continue;
+                        LGate mg = merge_1q(g, st.ops[li]);
+                        if (op_cost(mg) <= op_cost(g) + op_cost(st.ops[li])) {
+                            st.ops[li] = mg;
+                            continue;
+                        }
                     }
                 }
                 st.ops.push_back(g);
@@ -166,7 +195,11 @@ struct Packer {
             bool make_dense = false;
             if (dense_mode) {
                 make_dense = true;
-                st.mfma = W >= 4;  // the matrix-core stage needs k >= 4
+                // the matrix-core stage needs whole waves (b >= 10) and at
+                // least 16 columns per unitary (b - k >= 4); a 4-qubit
+                // unitary on smaller tiles runs on registers instead
+                st.mfma = pp.b >= 10 && pp.b - W >= 4;
+                if (!st.mfma && W != QK_G) throw std::invalid_argument("dense fusion width needs tile_bits >= 10");
             } else if (pp.fusion == QTASK_FUSE_AUTO && fl > dense_fl) {
                 make_dense = true;  // dense 16x16 on registers is cheaper than the list
             }
@@ -182,6 +215,27 @@ struct Packer {
             }
             ps.stages.push_back(std::move(st));
             rem.swap(left);
+        }
+    }
+
+    // Every pass has at least one stage, and its first and last stages use
+    // ascending thread-bit order: their thread bits then start at the lowest
+    // tile bits, which keeps their global loads and stores coalesced.
+    void finish_pass(PPass &ps) const {
+        auto empty_stage = [&] {
+            PStage st;
+            for (int p = pp.b - QK_G; p < pp.b; ++p) st.tbits.push_back(p);
+            return st;
+        };
+        // the first stage loads and the last one stores: both must be
+        // register stages
+        if (ps.stages.empty() || ps.stages.front().mfma) ps.stages.insert(ps.stages.begin(), empty_stage());
+        if (ps.stages.back().mfma) ps.stages.push_back(empty_stage());
+        for (const auto &st : ps.stages) ps.has_mfma = ps.has_mfma || st.mfma;
+        for (PStage *st : {&ps.stages.front(), &ps.stages.back()}) {
+            st->tpos.clear();
+            for (int p = 0; p < pp.b; ++p)
+                if (std::find(st->tbits.begin(), st->tbits.end(), p) == st->tbits.end()) st->tpos.push_back(p);
         }
     }
 
@@ -212,6 +266,7 @@ struct Packer {
             for (size_t idx : take) pops.push_back(ops[idx]);
             ps.n_gates = int(pops.size());
             pack_stages(ps, pops);
+            finish_pass(ps);
             passes.push_back(std::move(ps));
             rem.swap(left);
         }
@@ -251,19 +306,7 @@ void pack_blob(SegmentPlan &sp) {
         const PPass &ps = sp.passes[pi];
         KPass &P = kp[pi];
         std::memset(&P, 0, sizeof(P));
-        // load/store mapping: tile bits 0..n_thr-1 <- thread index, the top G bits <- register i
-        for (int k = 0; k < n_thr; ++k) {
-            P.g_thr[k] = uint64_t(1) << ps.qlist[k];
-            P.p_thr[k] = phys(k);
-        }
-        for (int i = 0; i < QK_NREG; ++i) {
-            uint64_t g = 0;
-            uint32_t p = 0;
-            for (int j = 0; j < G; ++j)
-                if ((i >> j) & 1) { g |= uint64_t(1) << ps.qlist[n_thr + j]; p ^= phys(n_thr + j); }
-            P.g_i[i] = g;
-            P.p_i[i] = p;
-        }
+        auto goff = [&](int p) { return uint64_t(1) << ps.qlist[p]; };
         int k = 0;
         for (int q = 0; q < pp.n; ++q)
             if (!((ps.qmask >> q) & 1)) P.nonq_pos[k++] = uint8_t(q);
@@ -275,6 +318,15 @@ void pack_blob(SegmentPlan &sp) {
             KStage &S = ks[si++];
             std::memset(&S, 0, sizeof(S));
             const int W = int(st.tbits.size());
+            if (!st.mfma) {
+                for (int i = 0; i < QK_NREG; ++i) {
+                    uint64_t g = 0;
+                    for (int j = 0; j < G; ++j)
+                        if ((i >> j) & 1) g |= goff(st.tbits[j]);
+                    S.g_reg[i] = g;
+                }
+                for (int j = 0; j < n_thr; ++j) S.g_thr[j] = goff(st.tpos[j]);
+            }
             if (st.mfma) {
                 S.kind = KSTAGE_MFMA;
                 S.k = uint32_t(W);
@@ -369,12 +421,13 @@ SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp) {
     sp.passes = pk.pack_passes(ops);
     if (sp.passes.empty()) {
         // a segment without gates still carries the state across its
-        // boundary (restore, checkpoint write, norm): one pass, no stages
+        // boundary (restore, checkpoint write, norm): one pass, one empty stage
         PPass ps;
         for (int q = 0; q < pp.b; ++q) {
             ps.qlist.push_back(q);
             ps.qmask |= uint64_t(1) << q;
         }
+        pk.finish_pass(ps);
         sp.passes.push_back(ps);
     }
     sp.n_gates = ops.size();
@@ -401,20 +454,26 @@ std::string validate_plan(const SegmentPlan &sp) {
         if (int(ps.qlist.size()) != b) { err << "pass " << pi << ": qlist size"; return err.str(); }
         for (int q = 0; q < std::max(0, std::min(pp.c, pp.b - 3)); ++q)
             if (ps.qlist[q] != q) { err << "pass " << pi << ": low bits"; return err.str(); }
-        std::vector<uint8_t> seen(tile, 0);
-        uint64_t gmask = 0;
-        for (uint32_t t = 0; t < (1u << n_thr); ++t) {
-            uint32_t pt = 0;
-            uint64_t gt = 0;
-            for (int k = 0; k < n_thr; ++k)
-                if ((t >> k) & 1) { pt ^= P.p_thr[k]; gt |= P.g_thr[k]; }
-            for (int i = 0; i < QK_NREG; ++i) {
-                const uint32_t s = pt ^ P.p_i[i];
-                if (s >= tile || seen[s]++) { err << "pass " << pi << ": load map"; return err.str(); }
-                gmask |= gt | P.g_i[i];
+        if (P.stage_count < 1) { err << "pass " << pi << ": no stage"; return err.str(); }
+        for (uint32_t which : {P.stage_begin, P.stage_begin + P.stage_count - 1}) {
+            const KStage &S = ks[which];
+            if (S.kind != KSTAGE_LIST) { err << "pass " << pi << ": first/last stage must be a list stage"; return err.str(); }
+            std::vector<uint64_t> offs;
+            uint64_t gmask = 0;
+            for (uint32_t t = 0; t < (1u << n_thr); ++t) {
+                uint64_t gt = 0;
+                for (int k = 0; k < n_thr; ++k)
+                    if ((t >> k) & 1) gt |= S.g_thr[k];
+                for (int i = 0; i < QK_NREG; ++i) {
+                    if (gt & S.g_reg[i]) { err << "pass " << pi << ": global map overlap"; return err.str(); }
+                    offs.push_back(gt | S.g_reg[i]);
+                    gmask |= gt | S.g_reg[i];
+                }
             }
+            std::sort(offs.begin(), offs.end());
+            if (std::unique(offs.begin(), offs.end()) != offs.end()) { err << "pass " << pi << ": global map not one-to-one"; return err.str(); }
+            if (gmask != ps.qmask) { err << "pass " << pi << ": global mask"; return err.str(); }
         }
-        if (gmask != ps.qmask) { err << "pass " << pi << ": global mask"; return err.str(); }
         for (uint32_t s = 0; s < P.stage_count; ++s) {
             const KStage &S = ks[P.stage_begin + s];
             const PStage &st = ps.stages[s];

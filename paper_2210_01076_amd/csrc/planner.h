@@ -35,6 +35,7 @@ struct PPass {
     std::vector<PStage> stages;
     uint64_t qmask = 0;
     int n_gates = 0;          // source gates applied in this pass
+    bool has_mfma = false;    // some stage runs on the matrix cores
 };
 
 struct SegmentPlan {

@@ -438,7 +438,7 @@ int Session::prepare(bool force_full) {
 
     // launch list
     size_t li = 0;
-    double bytes = 0, flops = 0;
+    double bytes = 0, flops = 0, mfma_flops = 0;
     for (size_t s = s0; s < S; ++s) {
         const SegmentPlan &sp = plans_[s];
         const int b = sp.pp.b;
@@ -464,6 +464,7 @@ int Session::prepare(bool force_full) {
             a.ops = reinterpret_cast<const KOp *>(blob + sp.off_op);
             a.coefs = blob + sp.off_coef;
             a.block_bits = uint32_t(std::min(opts.block_bits, n_int));
+            a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
             uint64_t tiles = full_tiles;
             if (mode == 3) {
                 tiles = list_off[li + 1] - list_off[li];
@@ -477,9 +478,13 @@ int Session::prepare(bool force_full) {
             if (tiles > 0 || L.after) launches.push_back(L);
             const double tb = double(uint64_t(1) << b) * double(elem);
             bytes += double(tiles) * tb * ((a.src_basis ? 0 : 1) + 1 + (a.ckpt ? 1 : 0));
-            double pf = 0;
-            for (const auto &stg : sp.passes[p].stages) pf += stg.flops;
+            double pf = 0, mf = 0;
+            for (const auto &stg : sp.passes[p].stages) {
+                pf += stg.flops;
+                if (stg.mfma) mf += stg.flops;
+            }
             flops += double(tiles) * double(uint64_t(1) << b) * pf;
+            mfma_flops += double(tiles) * double(uint64_t(1) << b) * mf;
             st.passes += 1;
             st.tiles += tiles;
             st.stages += sp.passes[p].stages.size();
@@ -489,6 +494,7 @@ int Session::prepare(bool force_full) {
     if (renorm && S > 0) bytes += 2.0 * double(state_bytes());
     st.bytes = bytes;
     st.flops = flops;
+    st.mfma_flops = mfma_flops;
     st.plan_ms = now_ms() - t0;
     last = st;
     return QTASK_OK;
@@ -540,6 +546,11 @@ int Session::update(bool force_full) {
     const double t0 = now_ms();
     int rc = init_device();
     if (rc != QTASK_OK) return rc;
+    if (opts.autotune && !tuned_ && !plan_only) {
+        rc = autotune();
+        if (rc != QTASK_OK) return rc;
+        tuned_ = true;
+    }
     rc = prepare(force_full);
     if (rc != QTASK_OK) {
         state_valid_ = false;

@@ -39,6 +39,7 @@ public:
     bool own_stream = false;
 
     int init_device();   // called lazily; creates stream, scratch
+    int autotune();      // picks opts.tile_bits / opts.low_bits by timing (first update)
     int update(bool force_full);
     int read(uint64_t first, uint64_t count, void *out);
     int norm(double *out);
@@ -99,6 +100,7 @@ private:
     uint32_t *d_tiles_ = nullptr;   size_t tiles_cap_ = 0;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
     bool dev_ready_ = false;
+    bool tuned_ = false;
 
     // prepared replay
     size_t prep_s0_ = 0, prep_S_ = 0;

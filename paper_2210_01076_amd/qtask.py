@@ -48,6 +48,7 @@ class qtask_stats(ctypes.Structure):
                 ("levels_replayed", u64), ("segments_replayed", u64), ("first_level", u64), ("passes", u64),
                 ("tiles", u64), ("stages", u64), ("dirty_blocks", u64), ("total_blocks", u64),
                 ("gate_amp_updates", u64), ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
+                ("mfma_flops", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("pass_kernel_ms", ctypes.c_double),
                 ("plan_ms", ctypes.c_double), ("wall_ms", ctypes.c_double)]
 
@@ -101,6 +102,7 @@ _SIGS = {
     "qtask_device_bytes": ([vp, P(u64)], ctypes.c_int),
     "qtask_get_opts": ([vp, P(qtask_opts)], ctypes.c_int),
     "qtask_dump_plan": ([vp, ctypes.c_char_p], ctypes.c_int),
+    "qtask_copy_bandwidth": ([ctypes.c_int, u64, ctypes.c_int, P(ctypes.c_double)], ctypes.c_int),
     "qtask_server_opts_default": ([P(qtask_server_opts)], ctypes.c_int),
     "qtask_server_create": ([P(qtask_server_opts), P(vp)], ctypes.c_int),
     "qtask_server_destroy": ([vp], ctypes.c_int),
@@ -272,6 +274,12 @@ def qtask_get_opts(h) -> qtask_opts:
 
 def qtask_dump_plan(h, path: str) -> None:
     check(load().qtask_dump_plan(h, path.encode()), "qtask_dump_plan")
+
+
+def qtask_copy_bandwidth(device: int = 0, nbytes: int = 1 << 30, iters: int = 20) -> float:
+    v = ctypes.c_double()
+    check(load().qtask_copy_bandwidth(device, nbytes, iters, ctypes.byref(v)), "qtask_copy_bandwidth")
+    return v.value
 
 
 # ------------------------------------------------------------- convenience

@@ -142,3 +142,19 @@ def test_worked_example_on_device():
         assert st["mode"] == 3 and st["dirty_blocks"] == 6
         np.testing.assert_allclose(s.state(), gold["uniform_amplitude"], atol=1e-15)
         _check_incremental(s, [[g for g in net] for net in nets], gold["n"], "c128", with_oracle=False)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dense_fusion_incremental_bitwise(dtype):
+    n = 14
+    nets = W.layered_circuit(n, 16, 12)
+    batches = W.modifier_batches(n, nets, 13, 5, 1, 3, W.LAYERED_EDIT_KINDS)
+    with sim(n, nets, dtype, tile_bits=10, low_bits=3, fusion=2, fuse_width=5, ckpt_interval=8) as s:
+        s.update()
+        for bi, batch in enumerate(batches):
+            for e in batch:
+                W.apply_edit(nets, e)
+                s.apply_edit(e)
+            s.update()
+            st = _check_incremental(s, nets, n, dtype, with_oracle=bi % 2 == 0)
+            log("dense-inc", dtype, bi, st["mode"])

@@ -130,3 +130,17 @@ def test_inner_product_and_norm(dtype):
         assert abs(got - want) < TOL[dtype] * 10
         assert Q.qtask_compare_states(a.h, a.h) == 0
         assert Q.qtask_compare_states(a.h, b.h) > 0
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("k,b", [(4, 10), (5, 10), (6, 11), (5, 12)])
+def test_dense_fusion_on_matrix_cores(dtype, k, b):
+    n = 15
+    nets = W.layered_circuit(n, 6, 31) + W.dense_random_circuit(n, 4, 32, kinds=W.GATE_KINDS)
+    want = oracle.simulate(n, nets, nthreads=oracle.max_threads())
+    log("dense", dtype, k, b)
+    with sim(n, nets, dtype, tile_bits=b, low_bits=3, fusion=Q.QTASK_FUSE_DENSE, fuse_width=k,
+             ckpt_interval=6) as s:
+        st = s.update()
+        assert st["mfma_flops"] > 0
+        check_state(s.state(), want, dtype, "dense k=%d b=%d" % (k, b))

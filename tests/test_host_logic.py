@@ -156,6 +156,31 @@ def test_planner_emulation_matches_oracle(n, b, c, seed, fam):
     assert sum(seg["gates"] for seg in dump["segments"]) == W.count_gates(nets)
 
 
+@pytest.mark.parametrize("k,b", [(4, 10), (5, 10), (6, 11), (5, 12), (4, 6)])
+def test_planner_dense_fusion_emulation(k, b):
+    n = 13
+    nets = W.layered_circuit(n, 5, 21) + W.dense_random_circuit(n, 4, 22, kinds=W.GATE_KINDS)
+    with plan_only(n, tile_bits=b, low_bits=3, fusion=Q.QTASK_FUSE_DENSE, fuse_width=k, ckpt_interval=6) as sim:
+        sim.build(nets)
+        sim.update()
+        dump = sim.dump()
+    stages = [st for seg in dump["segments"] for p in seg["passes"] for st in p["stages"]]
+    dense = [st for st in stages if st["dense"]]
+    assert dense and all(len(st["qubits"]) == k for st in dense)
+    if b >= 10:
+        assert all(st["mfma"] for st in dense)
+    for st in dense:
+        U = np.array([complex(a, c) for a, c in st["U"]]).reshape(1 << k, 1 << k)
+        np.testing.assert_allclose(U @ U.conj().T, np.eye(1 << k), atol=1e-13)
+    np.testing.assert_allclose(emulate(dump, n), oracle.simulate(n, nets), atol=1e-12)
+
+
+def test_dense_fusion_needs_large_tiles():
+    with pytest.raises(Q.QtaskError) as e:
+        plan_only(8, fusion=Q.QTASK_FUSE_DENSE, fuse_width=5)
+    assert e.value.code == Q.QTASK_E_UNSUPPORTED
+
+
 def test_planner_auto_fusion_makes_dense_stages():
     # deep circuit on 4 qubits: every stage is long enough to fuse
     rng = np.random.default_rng(11)
