@@ -38,10 +38,14 @@ def log(*a):
 
 def run_tier(Q, W, wl, dtype, steps, warmup):
     nets = [list(x) for x in wl.nets]
-    sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels)
+    sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=1)
     sim.build(nets)
-    st = sim.update()
+    t0 = time.perf_counter()
+    st = sim.update()          # first update: autotune + full simulation
+    tune_s = time.perf_counter() - t0
     first_full = st
+    o = Q.qtask_get_opts(sim.h)
+    log("%s tile shape b=%d c=%d (autotune + first full %.2f s)" % (dtype, o.tile_bits, o.low_bits, tune_s))
     for _ in range(warmup):
         sim.update(full=True)
     inc_ms, full_ms, speed, bound = [], [], [], []
@@ -88,6 +92,8 @@ def run_tier(Q, W, wl, dtype, steps, warmup):
         "pass_bytes": full_bytes / max(passes, 1),
         "gate_amp_updates_per_s": gate_amp / (full_wall * 1e-3),
         "first_full_ms": first_full["wall_ms"],
+        "tile_bits": o.tile_bits,
+        "low_bits": o.low_bits,
     }
     return sim, nets, out
 
@@ -177,7 +183,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "layered random circuit, 24 qubits, 200 levels (RX/RY/RZ on every qubit + random "
                                "CNOT matching), 100 batches of 1-4 random gate inserts/removals; complex128",
-                   "qubits": 24, "levels": 200, "batches": 100, "ckpt_levels": 50},
+                   "qubits": 24, "levels": 200, "batches": 100, "ckpt_levels": 50,
+                   "tile_bits": r128["tile_bits"], "low_bits": r128["low_bits"]},
         "frac_of_peak": round(r128["full_gbs"] / HBM_PEAK_GBS, 4),
         "copy_ceiling_gbs": round(copy_gbs, 1),
         "frac_of_copy_ceiling": round(r128["full_gbs"] / copy_gbs, 4),

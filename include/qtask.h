@@ -185,7 +185,9 @@ int qtask_last_update_stats(qtask_t h, qtask_stats *out);
 int qtask_read_amplitudes(qtask_t h, uint64_t first, uint64_t count, void *host_out);
 /* sum_b |alpha_b|^2 accumulated in FP64 with a fixed reduction order. */
 int qtask_norm(qtask_t h, double *out);
-/* <a|b> in FP64 (re, im); a and b must have the same n, dtype and device. */
+/* <a|b> accumulated in FP64 (re, im); a and b must have the same n and
+ * device; their dtypes may differ (a complex64 state against its complex128
+ * reference). */
 int qtask_inner(qtask_t a, qtask_t b, double re_im[2]);
 /* Number of amplitude slots whose bytes differ between a and b (bitwise). */
 int qtask_compare_states(qtask_t a, qtask_t b, uint64_t *n_diff);

@@ -251,7 +251,7 @@ int qtask_inner(qtask_t a, qtask_t b, double re_im[2]) {
     return guarded([&] {
         Session *x = S(a), *y = S(b);
         if (!x || !y || !re_im) return QTASK_E_ARG;
-        if (x->n != y->n || x->dtype != y->dtype) return QTASK_E_ARG;
+        if (x->n != y->n) return QTASK_E_ARG;
         if (x->plan_only || y->plan_only) return QTASK_E_UNSUPPORTED;
         if (x->opts.device != y->opts.device) return QTASK_E_ARG;
         if (!x->state_valid() || !y->state_valid() || x->circ.edited() || y->circ.edited()) return QTASK_E_STALE;
@@ -263,7 +263,7 @@ int qtask_inner(qtask_t a, qtask_t b, double re_im[2]) {
         if (hipStreamSynchronize(y->stream) != hipSuccess) { x->dfree(tmp); return QTASK_E_DEVICE; }
         int rc = QTASK_OK;
         double v[2] = {0, 0};
-        if (qtask::launch_inner(x->dtype, x->state(), y->state(), N, tmp + 2, tmp, x->stream) != hipSuccess ||
+        if (qtask::launch_inner(x->dtype, y->dtype, x->state(), y->state(), N, tmp + 2, tmp, x->stream) != hipSuccess ||
             hipMemcpyAsync(v, tmp, sizeof(v), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
             hipStreamSynchronize(x->stream) != hipSuccess)
             rc = QTASK_E_DEVICE;

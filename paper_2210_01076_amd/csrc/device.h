@@ -25,8 +25,8 @@ hipError_t launch_norm(int dtype, const void *state, uint64_t n, double *partial
 hipError_t launch_sum_partials(const double *partials, uint32_t n_partials, double *out, double *scale_out,
                                hipStream_t s);
 // <a|b> in FP64: out[0] = re, out[1] = im.  partials needs 2*reduce_grid(n) doubles.
-hipError_t launch_inner(int dtype, const void *a, const void *b, uint64_t n, double *partials, double *out,
-                        hipStream_t s);
+hipError_t launch_inner(int dtype_a, int dtype_b, const void *a, const void *b, uint64_t n, double *partials,
+                        double *out, hipStream_t s);
 // state *= (R)scale[0]
 hipError_t launch_scale(int dtype, void *state, uint64_t n, const double *scale, hipStream_t s);
 // Count elements whose bytes differ.  partials needs reduce_grid(n) uint64.

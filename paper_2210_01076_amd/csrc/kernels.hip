@@ -644,25 +644,27 @@ __global__ void __launch_bounds__(RED_THREADS) qk_norm_partials(const void *stat
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-template <typename R>
+template <typename RA, typename RB>
 __global__ void __launch_bounds__(RED_THREADS)
 qk_inner_partials(const void *a_, const void *b_, uint64_t n, double *partials) {
-    using C = typename V2<R>::T;
-    const C *a = static_cast<const C *>(a_);
-    const C *b = static_cast<const C *>(b_);
+    using CA = typename V2<RA>::T;
+    using CB = typename V2<RB>::T;
+    const CA *a = static_cast<const CA *>(a_);
+    const CB *b = static_cast<const CB *>(b_);
     const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const uint64_t beg = uint64_t(blockIdx.x) * chunk;
     const uint64_t end = beg + chunk < n ? beg + chunk : n;
     double re = 0, im = 0;
     for (uint64_t i = beg + threadIdx.x; i < end; i += RED_THREADS) {
-        const C x = a[i], y = b[i];
+        const CA x = a[i];
+        const CB y = b[i];
         const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
         re += xr * yr + xi * yi;
         im += xr * yi - xi * yr;
     }
     __shared__ double red[RED_THREADS / 64];
     const double tr = block_sum(re, red);
-    __syncthreads();
+    lds_barrier();
     const double ti = block_sum(im, red);
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = tr;
@@ -861,13 +863,18 @@ hipError_t launch_norm(int dtype, const void *state, uint64_t n, double *partial
     return launch_sum_partials(partials, g, out, scale_out, s);
 }
 
-hipError_t launch_inner(int dtype, const void *a, const void *b, uint64_t n, double *partials, double *out,
-                        hipStream_t s) {
+hipError_t launch_inner(int dtype_a, int dtype_b, const void *a, const void *b, uint64_t n, double *partials,
+                        double *out, hipStream_t s) {
     const uint32_t g = reduce_grid(n);
-    if (dtype == 0)
-        hipLaunchKernelGGL(qk_inner_partials<double>, dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
+    (void)hipGetLastError();
+    if (dtype_a == 0 && dtype_b == 0)
+        hipLaunchKernelGGL((qk_inner_partials<double, double>), dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
+    else if (dtype_a == 0)
+        hipLaunchKernelGGL((qk_inner_partials<double, float>), dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
+    else if (dtype_b == 0)
+        hipLaunchKernelGGL((qk_inner_partials<float, double>), dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
     else
-        hipLaunchKernelGGL(qk_inner_partials<float>, dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
+        hipLaunchKernelGGL((qk_inner_partials<float, float>), dim3(g), dim3(RED_THREADS), 0, s, a, b, n, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(qk_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, partials, g, 2u, out, (double *)nullptr);

@@ -220,24 +220,95 @@ int Session::try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan>
     }
     const auto &op = old_plans[s_edit].passes;
     const auto &np = plans_[s_edit].passes;
-    size_t pre = 0;
-    while (pre < op.size() && pre < np.size() && same_pass(op[pre], np[pre])) ++pre;
-    size_t suf = 0;
-    while (suf < op.size() - pre && suf < np.size() - pre &&
-           same_pass(op[op.size() - 1 - suf], np[np.size() - 1 - suf]))
-        ++suf;
+    // Cheap lower bound first: the blocks rewritten by the gates that were
+    // added or removed must be redone whatever else changed.  If even they
+    // reach every block, the replay cannot be restricted.
+    {
+        auto gate_key = [](const LGate &g) {
+            uint64_t id = 1469598103934665603ull ^ g.kop;
+            for (int q = 0; q < g.nq; ++q) id = (id ^ uint64_t(g.q[q] + 1)) * 1099511628211ull;
+            return id ^ g.gate_id;
+        };
+        std::vector<std::pair<uint64_t, const LGate *>> a, b;
+        for (const auto &p : op)
+            for (const auto &stg : p.stages)
+                for (const auto &g : stg.ops) a.emplace_back(gate_key(g), &g);
+        for (const auto &p : np)
+            for (const auto &stg : p.stages)
+                for (const auto &g : stg.ops) b.emplace_back(gate_key(g), &g);
+        auto by_key = [](const std::pair<uint64_t, const LGate *> &x, const std::pair<uint64_t, const LGate *> &y) {
+            return x.first < y.first;
+        };
+        std::sort(a.begin(), a.end(), by_key);
+        std::sort(b.begin(), b.end(), by_key);
+        BlockSet lb(nblocks);
+        size_t i = 0, j = 0;
+        auto add = [&](const LGate &g) { for_rewritten_blocks(g, beta, nblocks, [&](uint64_t k) { lb.set(k); }); };
+        while (i < a.size() || j < b.size()) {
+            if (j == b.size() || (i < a.size() && a[i].first < b[j].first)) add(*a[i++].second);
+            else if (i == a.size() || b[j].first < a[i].first) add(*b[j++].second);
+            else { ++i; ++j; }
+        }
+        bool sat = lb.all();
+        for (size_t s = s_edit; s < nseg && !sat; ++s)
+            for (const auto &p : plans_[s].passes) {
+                for_pass_ops(p, [&](const LGate &g) {
+                    if (!sat) {
+                        propagate(block_action(g, beta), lb);
+                        sat = lb.all();
+                    }
+                });
+                if (sat) break;
+            }
+        if (sat) return QTASK_E_UNSUPPORTED;
+    }
+    // Seeds: blocks whose ordered sequence of rewriting ops differs between
+    // the old and the new plan of the edited segment.  A block rewritten by
+    // the same ops in the same order from the same input ends with the same
+    // bits unless another block feeds it, which the propagation below covers.
+    size_t work = 0;
+    for (const auto *ps : {&op, &np})
+        for (const auto &p : *ps)
+            for (const auto &stg : p.stages) work += stg.U.empty() ? stg.ops.size() : 1;
+    if (work * nblocks > (uint64_t(1) << 28)) return QTASK_E_UNSUPPORTED;
+    auto seq_hash = [&](const std::vector<PPass> &passes) {
+        std::vector<uint64_t> h(nblocks, 0);
+        auto mix = [&](uint64_t j, uint64_t v) { h[j] = (h[j] ^ v) * 0x100000001b3ull + 0x9e3779b97f4a7c15ull; };
+        for (const auto &p : passes)
+            for (const auto &stg : p.stages) {
+                if (!stg.U.empty()) {
+                    uint64_t id = 1469598103934665603ull;
+                    for (const cd &z : stg.U) id = (id ^ std::hash<double>()(z.real()) ^ (std::hash<double>()(z.imag()) << 1)) * 1099511628211ull;
+                    for (int tb : stg.tbits) id = (id ^ uint64_t(p.qlist[tb])) * 1099511628211ull;
+                    for (uint64_t j = 0; j < nblocks; ++j) mix(j, id);
+                    continue;
+                }
+                for (const auto &g : stg.ops) {
+                    uint64_t id = 1469598103934665603ull ^ g.kop;
+                    for (int q = 0; q < g.nq; ++q) id = (id ^ uint64_t(g.q[q] + 1)) * 1099511628211ull;
+                    for (const cd &z : g.m) {
+                        uint64_t re, im;
+                        std::memcpy(&re, &z, 8);
+                        std::memcpy(&im, reinterpret_cast<const char *>(&z) + 8, 8);
+                        id = (id ^ re) * 1099511628211ull;
+                        id = (id ^ im) * 1099511628211ull;
+                    }
+                    for_rewritten_blocks(g, beta, nblocks, [&](uint64_t j) { mix(j, id); });
+                }
+            }
+        return h;
+    };
+    const std::vector<uint64_t> ho = seq_hash(op), hn = seq_hash(np);
     BlockSet d(nblocks);
-    for (size_t i = pre; i < op.size() - suf; ++i)
-        for_pass_ops(op[i], [&](const LGate &g) { add_touched(block_action(g, beta), d); });
-    for (size_t i = pre; i < np.size() - suf; ++i)
-        for_pass_ops(np[i], [&](const LGate &g) { add_touched(block_action(g, beta), d); });
+    for (uint64_t j = 0; j < nblocks; ++j)
+        if (ho[j] != hn[j]) d.set(j);
     bool saturated = d.all();
     auto prop = [&](const PPass &p) {
         if (saturated) return;
         for_pass_ops(p, [&](const LGate &g) { propagate(block_action(g, beta), d); });
         saturated = d.all();
     };
-    for (size_t i = np.size() - suf; i < np.size(); ++i) prop(np[i]);
+    for (size_t i = 0; i < np.size(); ++i) prop(np[i]);
     for (size_t s = s_edit + 1; s < nseg; ++s)
         for (const auto &p : plans_[s].passes) prop(p);
     if (saturated) return QTASK_E_UNSUPPORTED;

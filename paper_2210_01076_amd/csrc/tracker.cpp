@@ -73,6 +73,44 @@ BlockAction block_action(const LGate &g, int beta) {
     return a;
 }
 
+void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std::function<void(uint64_t)> &f) {
+    // required-one bits (as block-index bits) and, for SWAP, a pair that must differ
+    uint64_t need = 0;
+    bool all = false, swap_hi = false;
+    int sa = -1, sb = -1;
+    auto hb = [&](int q) { return q >= beta ? int(q - beta) : -1; };
+    switch (g.kop) {
+    case KOP_P1:
+        if (hb(g.q[0]) >= 0) need |= uint64_t(1) << hb(g.q[0]);
+        break;
+    case KOP_P2:
+        for (int j = 0; j < 2; ++j)
+            if (hb(g.q[j]) >= 0) need |= uint64_t(1) << hb(g.q[j]);
+        break;
+    case KOP_CX: case KOP_CU:
+        if (hb(g.q[0]) >= 0) need |= uint64_t(1) << hb(g.q[0]);
+        break;
+    case KOP_CCX:
+        for (int j = 0; j < 2; ++j)
+            if (hb(g.q[j]) >= 0) need |= uint64_t(1) << hb(g.q[j]);
+        break;
+    case KOP_SWAP:
+        sa = hb(g.q[0]);
+        sb = hb(g.q[1]);
+        swap_hi = sa >= 0 && sb >= 0;
+        break;
+    default:
+        all = true;
+        break;
+    }
+    for (uint64_t j = 0; j < nblocks; ++j) {
+        if (all) { f(j); continue; }
+        if ((j & need) != need) continue;
+        if (swap_hi && (((j >> sa) & 1) == ((j >> sb) & 1))) continue;
+        f(j);
+    }
+}
+
 namespace {
 // Visit every group of 2^nh blocks that differ only in the gate's high bits:
 // f(blocks[2^nh]) with blocks[h] the block index whose high part is h.

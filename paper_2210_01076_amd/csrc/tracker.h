@@ -11,6 +11,7 @@
 // couples with.
 #pragma once
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "lowering.h"
@@ -48,6 +49,12 @@ struct BlockAction {
 };
 
 BlockAction block_action(const LGate &g, int beta);
+
+// Blocks whose amplitudes the kernel rewrites when it runs this op (decided
+// by the op's kernel form, not by matrix values): controlled and phase ops
+// rewrite only the amplitudes with their control/phase bits set, every other
+// op rewrites its whole support.  Calls f(block) for each such block.
+void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std::function<void(uint64_t)> &f);
 
 // out |= blocks the gate can change
 void add_touched(const BlockAction &a, BlockSet &out);
