@@ -15,8 +15,17 @@ using qtask::Session;
 
 struct qtask_s {
     Session *s;
-    qtask_s *self;  // guards against stale handles
+    qtask_s *self;       // guards against stale handles
+    bool server_owned;   // owned by a server: queries only
 };
+
+namespace qtask {
+// used by the server, which owns the sessions it opens
+Session *session_of(qtask_t h) { return (h && h->self == h) ? h->s : nullptr; }
+void set_server_owned(qtask_t h, bool owned) {
+    if (h && h->self == h) h->server_owned = owned;
+}
+}  // namespace qtask
 
 namespace {
 
@@ -34,6 +43,14 @@ int guarded(F &&f) {
 Session *S(qtask_t h) {
     if (!h || h->self != h || !h->s) return nullptr;
     return h->s;
+}
+
+// handle for an entry point that changes the circuit or the state
+int SM(qtask_t h, Session **s) {
+    *s = S(h);
+    if (!*s) return QTASK_E_ARG;
+    if (h->server_owned) return QTASK_E_BUSY;
+    return QTASK_OK;
 }
 
 }  // namespace
@@ -135,7 +152,7 @@ int qtask_create(int n_qubits, qtask_dtype dtype, const qtask_opts *user, qtask_
             if (o.device >= count) return QTASK_E_DEVICE;
         }
         Session *s = new Session(n_qubits, int(dtype), o);
-        qtask_s *h = new qtask_s{s, nullptr};
+        qtask_s *h = new qtask_s{s, nullptr, false};
         h->self = h;
         *out = h;
         return QTASK_OK;
@@ -144,8 +161,8 @@ int qtask_create(int n_qubits, qtask_dtype dtype, const qtask_opts *user, qtask_
 
 int qtask_destroy(qtask_t h) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         delete s;
         h->s = nullptr;
         h->self = nullptr;
@@ -156,16 +173,16 @@ int qtask_destroy(qtask_t h) {
 
 int qtask_insert_level(qtask_t h, qtask_level_t after, qtask_level_t *out) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         return s->circ.insert_level(after, out);
     });
 }
 
 int qtask_remove_level(qtask_t h, qtask_level_t level) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         return s->circ.remove_level(level);
     });
 }
@@ -173,16 +190,16 @@ int qtask_remove_level(qtask_t h, qtask_level_t level) {
 int qtask_insert_gate(qtask_t h, qtask_level_t level, qtask_gate_kind kind, const int32_t *qubits, int nq,
                       const double *params, int np, qtask_gate_t *out) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         return s->circ.insert_gate(level, int(kind), qubits, nq, params, np, out);
     });
 }
 
 int qtask_remove_gate(qtask_t h, qtask_gate_t gate) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         return s->circ.remove_gate(gate);
     });
 }
@@ -209,8 +226,8 @@ int qtask_num_gates(qtask_t h, uint64_t *out) {
 
 int qtask_update_state(qtask_t h) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         return s->update(false);
     });
 }
@@ -218,8 +235,8 @@ int qtask_update_state(qtask_t h) {
 
 int qtask_update_state_full(qtask_t h) {
     return guarded([&] {
-        Session *s = S(h);
-        if (!s) return QTASK_E_ARG;
+        Session *s = nullptr;
+        if (int rc = SM(h, &s)) return rc;
         return s->update(true);
     });
 }

@@ -71,6 +71,7 @@ int Circuit::insert_gate(uint64_t level, int kind, const int32_t *qubits, int nq
     gates_.emplace(g.id, g);
     lv.gates.push_back(g.id);
     lv.qmask |= m;
+    ++lv.version;
     touch(size_t(i));
     *out = g.id;
     return QTASK_OK;
@@ -83,6 +84,7 @@ int Circuit::remove_gate(uint64_t gate) {
     Level &lv = levels_.at(g.level);
     for (int j = 0; j < g.nq; ++j) lv.qmask &= ~(uint64_t(1) << g.q[j]);
     lv.gates.erase(std::find(lv.gates.begin(), lv.gates.end(), gate));
+    ++lv.version;
     touch(size_t(index_of(g.level)));
     gates_.erase(it);
     return QTASK_OK;

@@ -20,6 +20,7 @@ struct Gate {
 
 struct Level {
     uint64_t id = 0;
+    uint64_t version = 0;             // bumped by every gate insert/remove in the level
     uint64_t qmask = 0;               // qubits used by its gates
     std::vector<uint64_t> gates;      // gate ids in insertion order
 };

@@ -10,10 +10,13 @@ namespace qtask {
 // One pass over `n_tiles` tiles of 2^b amplitudes (dtype 0: complex128, 1: complex64).
 hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s);
 
-// Batched small-session pass round: `n_items` items, `n_groups` workgroups in
-// total, `max_threads` threads and `lds_bytes` LDS per workgroup.
-hipError_t launch_pass_batch(int dtype, const KBatchItem *items, uint32_t n_items, uint32_t n_groups,
-                             uint32_t max_threads, uint32_t lds_bytes, hipStream_t s);
+// Batched small-session pass round: the item count is read from `count`
+// (device memory); `n_groups` workgroups of `threads` threads and
+// `lds_bytes` LDS each (items must all use that thread count).
+hipError_t launch_pass_batch(int dtype, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,
+                             uint32_t threads, uint32_t lds_bytes, hipStream_t s);
+// Batched renormalisation sums (one workgroup per item, count in device memory).
+hipError_t launch_batch_sums(const KSumItem *items, const uint32_t *count, uint32_t n_groups, hipStream_t s);
 
 // FP64 sum |a_i|^2 over n elements: partial sums over a fixed grid, then one
 // workgroup adds them in a fixed order.  out[0] = sum; when scale_out is not

@@ -105,3 +105,12 @@ struct KBatchItem {
     uint32_t threads;          // 2^(b - QK_G) threads used by this item
     uint32_t pad;
 };
+
+// Renormalisation sum of one batched item.
+struct KSumItem {
+    const double *partials;
+    double *norm_out;
+    double *scale_out;
+    uint32_t n;
+    uint32_t pad;
+};

@@ -592,21 +592,26 @@ qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, 
                      src_basis, block_bits, reinterpret_cast<C *>(smem));
 }
 
-// Batched pass round over many small sessions that share one tile shape:
-// each workgroup finds its item by binary search over the items' first
-// workgroup index.  Every decision below depends only on blockIdx, so a
+// Batched pass round over many small sessions that share one tile shape.
+// The item table and its length live in device memory, so a captured graph
+// of such launches can be replayed with new work each time.  Each workgroup
+// finds its item by binary search over the items' first workgroup index;
+// every decision below depends only on blockIdx and the table, so a
 // workgroup either runs the whole pass body or leaves before any barrier.
 template <typename R>
 __global__ void __launch_bounds__(512)
-qk_pass_batch(const KBatchItem *__restrict__ items, uint32_t n_items) {
+qk_pass_batch(const KBatchItem *__restrict__ items, const uint32_t *__restrict__ count) {
     extern __shared__ __align__(16) unsigned char smem[];
     using C = typename V2<R>::T;
+    const uint32_t n_items = count[0];
+    if (n_items == 0) return;
     uint32_t lo = 0, hi = n_items;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (items[mid].tile_begin <= blockIdx.x) lo = mid; else hi = mid;
     }
     const KBatchItem *it = items + lo;
+    if (blockIdx.x < it->tile_begin) return;
     const uint32_t local = blockIdx.x - it->tile_begin;
     if (local >= it->n_tiles || it->threads != blockDim.x) return;
     const KArgs &a = it->args;
@@ -614,6 +619,22 @@ qk_pass_batch(const KBatchItem *__restrict__ items, uint32_t n_items) {
     pass_body<R, false>(tile, local, a.dst, a.src, a.ckpt, a.pass, a.stages, a.ops,
                         static_cast<const R *>(a.coefs), a.store_mask, a.scale, a.partials, a.src_basis,
                         a.block_bits, reinterpret_cast<C *>(smem));
+}
+
+// Batched renormalisation sums: workgroup i adds the per-tile partials of
+// item i in a fixed order and writes the norm and 1/sqrt(norm).
+__global__ void __launch_bounds__(256)
+qk_batch_sums(const KSumItem *__restrict__ items, const uint32_t *__restrict__ count) {
+    if (blockIdx.x >= count[0]) return;
+    const KSumItem &it = items[blockIdx.x];
+    double acc = 0;
+    for (uint32_t i = threadIdx.x; i < it.n; i += 256) acc += it.partials[i];
+    __shared__ double red[4];
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        it.norm_out[0] = tot;
+        it.scale_out[0] = 1.0 / sqrt(tot);
+    }
 }
 
 // ------------------------------------------------------------- reductions
@@ -830,18 +851,24 @@ hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipSt
     return dtype == 0 ? launch_pass_t<double, false>(a, n_tiles, b, s) : launch_pass_t<float, false>(a, n_tiles, b, s);
 }
 
-hipError_t launch_pass_batch(int dtype, const KBatchItem *items, uint32_t n_items, uint32_t n_groups,
-                             uint32_t max_threads, uint32_t lds_bytes, hipStream_t s) {
+hipError_t launch_pass_batch(int dtype, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,
+                             uint32_t threads, uint32_t lds_bytes, hipStream_t s) {
     (void)hipGetLastError();
     if (dtype == 0) {
         hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<double>), lds_bytes);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(qk_pass_batch<double>, dim3(n_groups), dim3(max_threads), lds_bytes, s, items, n_items);
+        hipLaunchKernelGGL(qk_pass_batch<double>, dim3(n_groups), dim3(threads), lds_bytes, s, items, count);
     } else {
         hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<float>), lds_bytes);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(qk_pass_batch<float>, dim3(n_groups), dim3(max_threads), lds_bytes, s, items, n_items);
+        hipLaunchKernelGGL(qk_pass_batch<float>, dim3(n_groups), dim3(threads), lds_bytes, s, items, count);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sums(const KSumItem *items, const uint32_t *count, uint32_t n_groups, hipStream_t s) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(qk_batch_sums, dim3(n_groups), dim3(256), 0, s, items, count);
     return hipGetLastError();
 }
 

@@ -152,8 +152,14 @@ struct Packer {
         }
         std::vector<size_t> rem(ops.size());
         for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
+        // The first stage loads straight from HBM through its own register
+        // map, which is coalesced only when its registers avoid the lowest
+        // tile bits (those must vary across lanes).  So the first stage is
+        // packed from gates above them when there are any; the others wait.
+        const uint32_t low_mask = (1u << std::min(coalesce_bits(), pp.b - QK_G)) - 1;
+        bool first = true;
         while (!rem.empty()) {
-            uint32_t S = 0, blocked = 0;
+            uint32_t S = 0, blocked = first ? low_mask : 0;
             std::vector<size_t> take, left;
             for (size_t idx : rem) {
                 const uint32_t m = tmask[idx];
@@ -161,8 +167,13 @@ struct Packer {
                 if (popc(S | m) <= W) { S |= m; take.push_back(idx); }
                 else { blocked |= m; left.push_back(idx); }
             }
+            if (take.empty() && first) {
+                first = false;
+                continue;  // every pending gate touches the low bits
+            }
+            first = false;
             if (take.empty()) throw std::logic_error("stage packing made no progress");
-            for (int p = 0; p < pp.b && popc(S) < W; ++p) S |= 1u << p;
+            for (int p = pp.b - 1; p >= 0 && popc(S) < W; --p) S |= 1u << p;
             PStage st;
             for (int p = 0; p < pp.b; ++p)
                 if ((S >> p) & 1) st.tbits.push_back(p);
@@ -221,16 +232,28 @@ struct Packer {
     // Every pass has at least one stage, and its first and last stages use
     // ascending thread-bit order: their thread bits then start at the lowest
     // tile bits, which keeps their global loads and stores coalesced.
+    // tile bits that must vary across lanes for coalesced 128-byte segments
+    int coalesce_bits() const { return pp.dtype == 0 ? 3 : 4; }
+
     void finish_pass(PPass &ps) const {
         auto empty_stage = [&] {
             PStage st;
             for (int p = pp.b - QK_G; p < pp.b; ++p) st.tbits.push_back(p);
             return st;
         };
+        const int lowb = std::min(coalesce_bits(), pp.b - QK_G);
+        auto touches_low = [&](const PStage &st) {
+            for (int p : st.tbits)
+                if (p < lowb) return true;
+            return false;
+        };
         // the first stage loads and the last one stores: both must be
-        // register stages
-        if (ps.stages.empty() || ps.stages.front().mfma) ps.stages.insert(ps.stages.begin(), empty_stage());
-        if (ps.stages.back().mfma) ps.stages.push_back(empty_stage());
+        // register stages whose registers avoid the lowest tile bits; when
+        // they are not, a plain load (store) stage goes through LDS instead
+        if (ps.stages.empty() || ps.stages.front().mfma || touches_low(ps.stages.front()))
+            ps.stages.insert(ps.stages.begin(), empty_stage());
+        if (ps.stages.back().mfma || (ps.stages.size() > 1 && touches_low(ps.stages.back())))
+            ps.stages.push_back(empty_stage());
         for (const auto &st : ps.stages) ps.has_mfma = ps.has_mfma || st.mfma;
         for (PStage *st : {&ps.stages.front(), &ps.stages.back()}) {
             st->tpos.clear();

@@ -46,9 +46,9 @@ Session::~Session() {
     if (plan_only) return;
     (void)hipSetDevice(opts.device);
     if (stream) (void)hipStreamSynchronize(stream);
-    for (auto &sp : plans_) dfree(sp.dev);
+    for (auto &kv : plan_cache_) dfree(kv.second.dev);
     dfree(state_.p);
-    for (auto &c : ckpt_) dfree(c.p);
+    for (auto &kv : ckpts_) dfree(kv.second.buf.p);
     dfree(d_partials_);
     dfree(d_scalars_);
     dfree(d_u64_);
@@ -110,15 +110,13 @@ uint64_t Session::planned_bytes() const {
 
 uint64_t Session::device_bytes() const {
     uint64_t b = state_.bytes;
-    for (const auto &c : ckpt_) b += c.bytes;
-    for (const auto &sp : plans_) b += sp.dev_bytes;
+    for (const auto &kv : ckpts_) b += kv.second.buf.bytes;
+    for (const auto &kv : plan_cache_) b += kv.second.dev_bytes;
     return b;
 }
 
-std::vector<LGate> Session::segment_ops(size_t s) const {
+std::vector<LGate> Session::level_ops(size_t lo, size_t hi) const {
     std::vector<LGate> ops;
-    const size_t lo = s * size_t(K());
-    const size_t hi = std::min(circ.num_levels(), lo + size_t(K()));
     for (size_t li = lo; li < hi; ++li) {
         const Level &lv = circ.level_by_index(li);
         std::vector<const Gate *> gs;
@@ -135,24 +133,87 @@ std::vector<LGate> Session::segment_ops(size_t s) const {
     return ops;
 }
 
+// Cut the circuit at its anchor levels.  The first time (no anchors) every
+// K-th level becomes an anchor; levels appended after the last anchor are cut
+// every K levels; a segment that grew to 2K levels through insertions is split.
+void Session::build_segments(const PlanParams &pp) {
+    segs_.clear();
+    const size_t D = circ.num_levels();
+    const size_t Kz = size_t(K());
+    size_t last_anchor = SIZE_MAX;
+    for (size_t i = 0; i < D; ++i)
+        if (anchors_.count(circ.level_by_index(i).id)) last_anchor = i;
+    std::unordered_set<uint64_t> used;
+    size_t lo = 0;
+    for (size_t i = 0; i < D; ++i) {
+        const uint64_t id = circ.level_by_index(i).id;
+        const size_t len = i - lo + 1;
+        const bool tail = last_anchor == SIZE_MAX || i > last_anchor;
+        const bool cut = anchors_.count(id) || len >= 2 * Kz || (tail && len >= Kz);
+        if (cut && i + 1 < D) {
+            Seg sg;
+            sg.lo = lo;
+            sg.hi = i + 1;
+            sg.anchor = id;
+            segs_.push_back(sg);
+            used.insert(id);
+            lo = i + 1;
+        }
+    }
+    if (D > 0) {
+        Seg sg;
+        sg.lo = lo;
+        sg.hi = D;
+        sg.anchor = 0;
+        segs_.push_back(sg);
+    }
+    anchors_ = used;
+    for (auto &sg : segs_) {
+        uint64_t k = 1469598103934665603ull;
+        auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
+        mix(uint64_t(pp.b) | uint64_t(pp.c) << 8 | uint64_t(pp.fusion) << 16 | uint64_t(pp.fuse_k) << 24 |
+            uint64_t(pp.dtype) << 32);
+        for (size_t i = sg.lo; i < sg.hi; ++i) {
+            const Level &lv = circ.level_by_index(i);
+            mix(lv.id);
+            mix(lv.version);
+        }
+        sg.key = k;
+    }
+}
+
+size_t Session::slot_of(uint64_t anchor) {
+    if (anchor == 0) return 0;
+    auto it = slots_.find(anchor);
+    if (it != slots_.end()) return it->second;
+    const size_t sl = next_slot_++;
+    slots_.emplace(anchor, sl);
+    return sl;
+}
+
+int Session::ensure_scalars(size_t slots) {
+    if (plan_only || scalars_cap_ / 2 >= slots) return QTASK_OK;
+    const size_t half = std::max<size_t>(2 * slots, 64);
+    double *p = static_cast<double *>(dalloc(2 * half * sizeof(double)));
+    if (!p) return QTASK_E_NOMEM;
+    if (d_scalars_) {
+        // keep the norms and scales of still-valid checkpoints
+        const size_t old = scalars_cap_ / 2;
+        HIPCHK(hipMemcpyAsync(p, d_scalars_, old * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        HIPCHK(hipMemcpyAsync(p + half, d_scalars_ + old, old * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        dfree(d_scalars_);
+    }
+    d_scalars_ = p;
+    scalars_cap_ = 2 * half;
+    return QTASK_OK;
+}
+
 int Session::ensure_state() {
     if (state_.p) return QTASK_OK;
     state_.p = dalloc(state_bytes());
     if (!state_.p) return QTASK_E_NOMEM;
     state_.bytes = state_bytes();
-    return QTASK_OK;
-}
-
-int Session::ensure_ckpt(size_t j) {
-    if (ckpt_.size() <= j) {
-        ckpt_.resize(j + 1);
-        ckpt_valid_.resize(j + 1, 0);
-    }
-    if (ckpt_[j].p) return QTASK_OK;
-    ckpt_[j].p = dalloc(state_bytes());
-    if (!ckpt_[j].p) return QTASK_E_NOMEM;
-    ckpt_[j].bytes = state_bytes();
-    ckpt_valid_[j] = 0;
     return QTASK_OK;
 }
 
@@ -203,23 +264,31 @@ uint64_t pext_tile(uint64_t x, const uint8_t *pos, uint32_t npos) {
 }  // namespace
 
 // Decide whether the replay can be restricted to a closed block set; fills S.
-int Session::try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan> &old_plans, BlockSet &S) {
+int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     const int beta = std::min(opts.block_bits, n_int);
     const uint64_t nblocks = uint64_t(1) << (n_int - beta);
     if (nblocks > (uint64_t(1) << 22)) return QTASK_E_UNSUPPORTED;
-    const size_t nseg = plans_.size();
-    if (s_edit >= nseg || s_edit >= old_plans.size()) return QTASK_E_UNSUPPORTED;
-    // every other segment from s0 on must be unchanged
-    for (size_t s = s0; s < nseg; ++s) {
-        if (s == s_edit) continue;
-        if (s >= old_plans.size() || old_plans[s].hash != plans_[s].hash) return QTASK_E_UNSUPPORTED;
-    }
-    if (old_plans[s_edit].hash == plans_[s_edit].hash) {
+    const size_t nseg = segs_.size();
+    if (s_edit >= nseg) return QTASK_E_UNSUPPORTED;
+    // the segments after the edited one must be the same as at the last
+    // update (same content, same anchors); match them from the end
+    const size_t tail = nseg - s_edit;
+    if (prev_hashes_.size() < tail) return QTASK_E_UNSUPPORTED;
+    const size_t oe = prev_hashes_.size() - tail;
+    for (size_t k = 1; k < tail; ++k)
+        if (prev_hashes_[oe + k] != segs_[s_edit + k].hash) return QTASK_E_UNSUPPORTED;
+    // and the segments from the restart point up to the edited one as well
+    if (oe < s_edit - s0) return QTASK_E_UNSUPPORTED;
+    for (size_t k = 1; k <= s_edit - s0; ++k)
+        if (prev_hashes_[oe - k] != segs_[s_edit - k].hash) return QTASK_E_UNSUPPORTED;
+    if (prev_hashes_[oe] == segs_[s_edit].hash) {
         S = BlockSet(nblocks);  // the edits cancelled out: nothing to redo
         return QTASK_OK;
     }
-    const auto &op = old_plans[s_edit].passes;
-    const auto &np = plans_[s_edit].passes;
+    auto old_it = plan_cache_.find(prev_hashes_[oe]);
+    if (old_it == plan_cache_.end()) return QTASK_E_UNSUPPORTED;
+    const auto &op = old_it->second.passes;
+    const auto &np = plans_[s_edit]->passes;
     // Cheap lower bound first: the blocks rewritten by the gates that were
     // added or removed must be redone whatever else changed.  If even they
     // reach every block, the replay cannot be restricted.
@@ -251,7 +320,7 @@ int Session::try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan>
         }
         bool sat = lb.all();
         for (size_t s = s_edit; s < nseg && !sat; ++s)
-            for (const auto &p : plans_[s].passes) {
+            for (const auto &p : plans_[s]->passes) {
                 for_pass_ops(p, [&](const LGate &g) {
                     if (!sat) {
                         propagate(block_action(g, beta), lb);
@@ -310,11 +379,11 @@ int Session::try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan>
     };
     for (size_t i = 0; i < np.size(); ++i) prop(np[i]);
     for (size_t s = s_edit + 1; s < nseg; ++s)
-        for (const auto &p : plans_[s].passes) prop(p);
+        for (const auto &p : plans_[s]->passes) prop(p);
     if (saturated) return QTASK_E_UNSUPPORTED;
     // closedness over every replayed gate
     for (size_t s = s0; s < nseg; ++s)
-        for (const auto &p : plans_[s].passes) {
+        for (const auto &p : plans_[s]->passes) {
             bool ok = true;
             for_pass_ops(p, [&](const LGate &g) {
                 if (ok && !closed_under(block_action(g, beta), d)) ok = false;
@@ -332,10 +401,8 @@ int Session::prepare(bool force_full) {
     qtask_stats st{};
     st.struct_size = sizeof(st);
     const size_t D = circ.num_levels();
-    const size_t S = num_segments();
     st.levels_total = D;
     st.total_blocks = uint64_t(1) << (n_int - std::min(opts.block_bits, n_int));
-    prep_S_ = S;
     prep_mode_ = 0;
     prep_tiles_.clear();
 
@@ -349,81 +416,92 @@ int Session::prepare(bool force_full) {
     pp.swz = dtype == QTASK_C128 ? 4 : 5;
 
     const bool full = force_full || !have_result_;
+    if (!full && !circ.edited()) {
+        st.plan_ms = now_ms() - t0;
+        last = st;
+        return QTASK_OK;  // mode 0: nothing to do
+    }
+    const size_t L = full ? 0 : circ.first_edited();
+    prep_first_edit_ = L;
+
+    // segments and their plans (cached by content)
+    build_segments(pp);
+    const size_t S = segs_.size();
+    prep_S_ = S;
+    plans_.assign(S, nullptr);
+    for (size_t s = 0; s < S; ++s) {
+        Seg &sg = segs_[s];
+        auto kh = key_hash_.find(sg.key);
+        if (kh != key_hash_.end() && plan_cache_.count(kh->second)) {
+            sg.hash = kh->second;
+        } else {
+            std::vector<LGate> ops = level_ops(sg.lo, sg.hi);
+            sg.hash = segment_hash(ops, pp);
+            key_hash_[sg.key] = sg.hash;
+            if (!plan_cache_.count(sg.hash)) {
+                SegmentPlan np;
+                try {
+                    np = plan_segment(ops, pp);
+                } catch (const std::exception &e) {
+                    last_error = e.what();
+                    return QTASK_E_ARG;
+                }
+                int rc = upload_plan(np);
+                if (rc != QTASK_OK) return rc;
+                plan_cache_.emplace(sg.hash, std::move(np));
+            }
+        }
+        plans_[s] = &plan_cache_.at(sg.hash);
+    }
+
+    // restart point: the newest valid checkpoint at or before the first
+    // edited level (boundary j = the state before segment j)
     size_t s0 = 0, s_edit = 0;
     if (!full) {
-        if (!circ.edited()) {
-            st.plan_ms = now_ms() - t0;
-            last = st;
-            return QTASK_OK;  // mode 0: nothing to do
-        }
-        const size_t L = circ.first_edited();
-        s_edit = L / size_t(K());
-        const size_t jmax = std::min(s_edit, S ? S - 1 : 0);
-        for (size_t j = jmax; j >= 1; --j)
-            if (stores_ckpt(j, S) && j < ckpt_valid_.size() && ckpt_valid_[j] && (plan_only || ckpt_[j].p)) {
+        s_edit = S ? S - 1 : 0;
+        for (size_t s = 0; s < S; ++s)
+            if (segs_[s].hi > L) { s_edit = s; break; }
+        for (size_t j = s_edit; j >= 1; --j) {
+            auto it = ckpts_.find(segs_[j - 1].anchor);
+            if (stores_ckpt(j, S) && it != ckpts_.end() && it->second.valid && segs_[j - 1].hi <= L &&
+                (plan_only || it->second.buf.p)) {
                 s0 = j;
                 break;
             }
-    }
-    // (re)plan segments s0..S-1; keep the replaced plans for the tracker
-    std::vector<SegmentPlan> old_plans;
-    if (plans_.size() > S) {
-        for (size_t s = S; s < plans_.size(); ++s) dfree(plans_[s].dev);
-    }
-    old_plans.resize(std::max(plans_.size(), S));
-    for (size_t s = s0; s < plans_.size(); ++s) old_plans[s].hash = plans_[s].hash;
-    plans_.resize(S);
-    for (size_t s = s0; s < S; ++s) {
-        std::vector<LGate> ops = segment_ops(s);
-        const uint64_t h = segment_hash(ops, pp);
-        if (plans_[s].hash == h && (plan_only || plans_[s].dev)) {
-            old_plans[s].hash = h;
-            continue;
         }
-        SegmentPlan np;
-        try {
-            np = plan_segment(ops, pp);
-        } catch (const std::exception &e) {
-            last_error = e.what();
-            return QTASK_E_ARG;
-        }
-        int rc = upload_plan(np);
-        if (rc != QTASK_OK) return rc;
-        dfree(plans_[s].dev);
-        plans_[s].dev = nullptr;
-        old_plans[s] = std::move(plans_[s]);
-        plans_[s] = std::move(np);
     }
-    // memory
+
+    // memory: state, checkpoints of the stored boundaries, scalars
+    for (auto it = ckpts_.begin(); it != ckpts_.end();) {
+        bool keep = false;
+        for (size_t j = 1; j < S; ++j)
+            if (segs_[j - 1].anchor == it->first && stores_ckpt(j, S)) keep = true;
+        if (!keep) {
+            dfree(it->second.buf.p);
+            it = ckpts_.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (size_t j = 1; j < S; ++j) {
+        if (!stores_ckpt(j, S)) continue;
+        Ckpt &ck = ckpts_[segs_[j - 1].anchor];
+        if (!plan_only && !ck.buf.p) {
+            ck.buf.p = dalloc(state_bytes());
+            if (!ck.buf.p) {
+                ckpts_.erase(segs_[j - 1].anchor);
+                return QTASK_E_NOMEM;
+            }
+            ck.buf.bytes = state_bytes();
+            ck.valid = false;
+        }
+    }
+    for (size_t j = 1; j < S; ++j) (void)slot_of(segs_[j - 1].anchor);
     if (!plan_only) {
         int rc = ensure_state();
         if (rc != QTASK_OK) return rc;
-        for (size_t j = 1; j < S; ++j)
-            if (stores_ckpt(j, S)) {
-                rc = ensure_ckpt(j);
-                if (rc != QTASK_OK) return rc;
-            }
-        for (size_t j = 0; j < ckpt_.size(); ++j)
-            if (!stores_ckpt(j, S) && ckpt_[j].p) {
-                dfree(ckpt_[j].p);
-                ckpt_[j] = DevBuf{};
-                ckpt_valid_[j] = 0;
-            }
-        if (scalars_cap_ < 2 * (S + 1)) {
-            const size_t cap = 2 * (S + 64);
-            double *p = static_cast<double *>(dalloc(cap * sizeof(double)));
-            if (!p) return QTASK_E_NOMEM;
-            if (d_scalars_) {
-                // keep the norms/scales of still-valid checkpoints
-                HIPCHK(hipMemcpyAsync(p, d_scalars_, scalars_cap_ / 2 * sizeof(double), hipMemcpyDeviceToDevice, stream));
-                HIPCHK(hipMemcpyAsync(p + cap / 2, d_scalars_ + scalars_cap_ / 2, scalars_cap_ / 2 * sizeof(double),
-                                      hipMemcpyDeviceToDevice, stream));
-                HIPCHK(hipStreamSynchronize(stream));
-                dfree(d_scalars_);
-            }
-            d_scalars_ = p;
-            scalars_cap_ = cap;
-        }
+        rc = ensure_scalars(next_slot_ + 1);
+        if (rc != QTASK_OK) return rc;
         const uint64_t max_tiles = uint64_t(1) << (n_int - pp.b);
         const size_t need = std::max<size_t>(max_tiles, 4096);
         if (partials_cap_ < need) {
@@ -443,14 +521,14 @@ int Session::prepare(bool force_full) {
     int mode = full ? 1 : 2;
     BlockSet set;
     if (!full && opts.closed_mode && !renorm && S > 0) {
-        if (try_closed(s0, s_edit, old_plans, set) == QTASK_OK) mode = 3;
+        if (try_closed(s0, s_edit, set) == QTASK_OK) mode = 3;
     }
     prep_mode_ = mode;
     prep_s0_ = s0;
     st.mode = mode;
-    st.first_level = s0 * size_t(K());
+    st.first_level = S ? segs_[s0].lo : 0;
     st.segments_replayed = S - s0;
-    st.levels_replayed = D - std::min(D, st.first_level);
+    st.levels_replayed = D - std::min(D, size_t(st.first_level));
     st.dirty_blocks = mode == 3 ? set.count() : st.total_blocks;
     if (mode == 3) prep_set_ = set;
 
@@ -460,9 +538,9 @@ int Session::prepare(bool force_full) {
         const int beta = std::min(opts.block_bits, n_int);
         const std::vector<uint32_t> blocks = set.list();
         for (size_t s = s0; s < S; ++s)
-            for (size_t p = 0; p < plans_[s].passes.size(); ++p) {
-                const PPass &ps = plans_[s].passes[p];
-                const KPass &kp = reinterpret_cast<const KPass *>(plans_[s].blob.data())[p];
+            for (size_t p = 0; p < plans_[s]->passes.size(); ++p) {
+                const PPass &ps = plans_[s]->passes[p];
+                const KPass &kp = reinterpret_cast<const KPass *>(plans_[s]->blob.data())[p];
                 uint64_t nonq_low = 0;
                 for (int q = 0; q < beta; ++q)
                     if (!((ps.qmask >> q) & 1)) nonq_low |= uint64_t(1) << q;
@@ -510,25 +588,29 @@ int Session::prepare(bool force_full) {
     // launch list
     size_t li = 0;
     double bytes = 0, flops = 0, mfma_flops = 0;
+    double *scales = plan_only ? nullptr : d_scalars_ + scalars_cap_ / 2;
     for (size_t s = s0; s < S; ++s) {
-        const SegmentPlan &sp = plans_[s];
+        const SegmentPlan &sp = *plans_[s];
         const int b = sp.pp.b;
         const uint64_t full_tiles = uint64_t(1) << (n_int - b);
         const char *blob = static_cast<const char *>(sp.dev);
         const size_t P = sp.passes.size();
+        const size_t end_slot = s + 1 < S ? slot_of(segs_[s].anchor) : 0;
+        void *end_ckpt = nullptr;
+        if (s + 1 < S && stores_ckpt(s + 1, S) && !plan_only) end_ckpt = ckpts_.at(segs_[s].anchor).buf.p;
         for (size_t p = 0; p < P; ++p, ++li) {
             Launch L{};
             KArgs &a = L.args;
             a.dst = state_.p;
             if (s == s0 && p == 0) {
                 if (s0 == 0) { a.src_basis = 1; a.src = nullptr; }
-                else a.src = plan_only ? nullptr : ckpt_[s0].p;
+                else a.src = plan_only ? nullptr : ckpts_.at(segs_[s0 - 1].anchor).buf.p;
             } else {
                 a.src = state_.p;
             }
             const bool lastp = p + 1 == P;
-            a.scale = (renorm && p == 0 && s > 0 && !plan_only) ? d_scalars_ + scalars_cap_ / 2 + s : nullptr;
-            a.ckpt = (lastp && s + 1 < S && stores_ckpt(s + 1, S) && !plan_only) ? ckpt_[s + 1].p : nullptr;
+            a.scale = (renorm && p == 0 && s > 0 && !plan_only) ? scales + slot_of(segs_[s - 1].anchor) : nullptr;
+            a.ckpt = lastp ? end_ckpt : nullptr;
             a.partials = (lastp && renorm) ? d_partials_ : nullptr;
             a.pass = reinterpret_cast<const KPass *>(blob) + p;
             a.stages = reinterpret_cast<const KStage *>(blob + sp.off_stage);
@@ -545,7 +627,7 @@ int Session::prepare(bool force_full) {
             L.n_tiles = uint32_t(tiles);
             L.b = b;
             L.after = (lastp && renorm) ? 1 : 0;
-            L.seg = int(s);
+            L.slot = end_slot;
             if (tiles > 0 || L.after) launches.push_back(L);
             const double tb = double(uint64_t(1) << b) * double(elem);
             bytes += double(tiles) * tb * ((a.src_basis ? 0 : 1) + 1 + (a.ckpt ? 1 : 0));
@@ -566,6 +648,21 @@ int Session::prepare(bool force_full) {
     st.bytes = bytes;
     st.flops = flops;
     st.mfma_flops = mfma_flops;
+    // drop cached plans no segment uses any more
+    {
+        std::unordered_set<uint64_t> live;
+        for (const auto &sg : segs_) live.insert(sg.hash);
+        for (auto it = plan_cache_.begin(); it != plan_cache_.end();) {
+            if (!live.count(it->first)) {
+                dfree(it->second.dev);
+                it = plan_cache_.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        for (auto it = key_hash_.begin(); it != key_hash_.end();)
+            it = live.count(it->second) ? std::next(it) : key_hash_.erase(it);
+    }
     st.plan_ms = now_ms() - t0;
     last = st;
     return QTASK_OK;
@@ -575,7 +672,7 @@ int Session::enqueue_after(const Launch &L, hipStream_t s) {
     if (L.after == 1) {
         double *norms = d_scalars_;
         double *scales = d_scalars_ + scalars_cap_ / 2;
-        HIPCHK(launch_sum_partials(d_partials_, L.n_tiles, norms + L.seg + 1, scales + L.seg + 1, s));
+        HIPCHK(launch_sum_partials(d_partials_, L.n_tiles, norms + L.slot, scales + L.slot, s));
     }
     return QTASK_OK;
 }
@@ -584,7 +681,8 @@ int Session::enqueue_final(hipStream_t s) {
     if (prep_S_ == 0) {
         HIPCHK(launch_fill_basis(dtype, state_.p, uint64_t(1) << n_int, s));
     } else if (prep_renorm_ && prep_mode_ != 0) {
-        HIPCHK(launch_scale(dtype, state_.p, uint64_t(1) << n_int, d_scalars_ + scalars_cap_ / 2 + prep_S_, s));
+        // slot 0 holds the scale computed at the end of the circuit
+        HIPCHK(launch_scale(dtype, state_.p, uint64_t(1) << n_int, d_scalars_ + scalars_cap_ / 2, s));
     }
     return QTASK_OK;
 }
@@ -601,27 +699,42 @@ int Session::enqueue_prepared(hipStream_t s) {
 int Session::finish_prepared_host() {
     if (prep_mode_ == 0) return QTASK_OK;
     const size_t S = prep_S_;
-    if (ckpt_valid_.size() < S) ckpt_valid_.resize(S, 0);
-    for (size_t j = 0; j < ckpt_valid_.size(); ++j) {
-        if (j >= S || !stores_ckpt(j, S)) ckpt_valid_[j] = 0;
-        else if (j > prep_s0_) ckpt_valid_[j] = 1;
-        // j <= s0: unchanged (valid if it was)
+    for (size_t j = 1; j < S; ++j) {
+        auto it = ckpts_.find(segs_[j - 1].anchor);
+        if (it == ckpts_.end()) continue;
+        // j > s0: rewritten by this replay -- wholly in modes 1 and 2; in
+        // mode 3 only the affected blocks were stored, which keeps a valid
+        // checkpoint valid (its other blocks are unchanged) and cannot make
+        // an invalid one valid.  j <= s0: unchanged, valid if it was.
+        if (j > prep_s0_ && prep_mode_ != 3) it->second.valid = true;
     }
+    prev_hashes_.clear();
+    for (const auto &sg : segs_) prev_hashes_.push_back(sg.hash);
     circ.clear_edits();
     have_result_ = true;
     state_valid_ = !plan_only;
     return QTASK_OK;
 }
 
+void Session::invalidate() {
+    state_valid_ = false;
+    have_result_ = false;
+    for (auto &kv : ckpts_) kv.second.valid = false;
+}
+
+int Session::ensure_tuned() {
+    if (!opts.autotune || tuned_ || plan_only) return QTASK_OK;
+    const int rc = autotune();
+    if (rc == QTASK_OK) tuned_ = true;
+    return rc;
+}
+
 int Session::update(bool force_full) {
     const double t0 = now_ms();
     int rc = init_device();
     if (rc != QTASK_OK) return rc;
-    if (opts.autotune && !tuned_ && !plan_only) {
-        rc = autotune();
-        if (rc != QTASK_OK) return rc;
-        tuned_ = true;
-    }
+    rc = ensure_tuned();
+    if (rc != QTASK_OK) return rc;
     rc = prepare(force_full);
     if (rc != QTASK_OK) {
         state_valid_ = false;
@@ -634,9 +747,7 @@ int Session::update(bool force_full) {
     }
     if (!plan_only) {
         auto fail = [&](int code) {
-            state_valid_ = false;
-            have_result_ = false;
-            for (auto &v : ckpt_valid_) v = 0;
+            invalidate();
             return code;
         };
         if (hipEventRecord(ev0_, stream) != hipSuccess) return fail(QTASK_E_DEVICE);
@@ -660,6 +771,27 @@ int Session::update(bool force_full) {
     finish_prepared_host();
     last.wall_ms = now_ms() - t0;
     return QTASK_OK;
+}
+
+void Session::release_device() {
+    if (plan_only) return;
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &kv : plan_cache_) dfree(kv.second.dev);
+    plan_cache_.clear();
+    key_hash_.clear();
+    plans_.clear();
+    prev_hashes_.clear();
+    for (auto &kv : ckpts_) dfree(kv.second.buf.p);
+    ckpts_.clear();
+    dfree(state_.p);
+    state_ = DevBuf{};
+    dfree(d_partials_); d_partials_ = nullptr; partials_cap_ = 0;
+    dfree(d_scalars_); d_scalars_ = nullptr; scalars_cap_ = 0;
+    dfree(d_u64_); d_u64_ = nullptr; u64_cap_ = 0;
+    dfree(d_mask_); d_mask_ = nullptr; mask_cap_ = 0;
+    dfree(d_tiles_); d_tiles_ = nullptr; tiles_cap_ = 0;
+    state_valid_ = false;
+    have_result_ = false;
 }
 
 int Session::read(uint64_t first, uint64_t count, void *out) {
@@ -719,7 +851,7 @@ int Session::dump(const char *path) {
     o << "],\"segments\":[";
     for (size_t s = 0; s < plans_.size(); ++s) {
         if (s) o << ",";
-        o << plan_json(plans_[s], true);
+        o << plan_json(*plans_[s], true);
     }
     o << "]}";
     FILE *f = std::fopen(path, "w");

@@ -6,6 +6,8 @@
 #include <chrono>
 #include <memory>
 #include <string>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/qtask.h"
@@ -40,6 +42,10 @@ public:
 
     int init_device();   // called lazily; creates stream, scratch
     int autotune();      // picks opts.tile_bits / opts.low_bits by timing (first update)
+    int ensure_tuned();  // autotune() once, when opts.autotune asks for it
+    // forget the state and every checkpoint (after a failed replay): the
+    // next update re-simulates from the start
+    void invalidate();
     int update(bool force_full);
     int read(uint64_t first, uint64_t count, void *out);
     int norm(double *out);
@@ -57,14 +63,26 @@ public:
         KArgs args;
         uint32_t n_tiles;
         int b;
-        int after;          // 0 none, 1 sum partials -> renorm scale of `seg+1`
-        int seg;
+        int after;          // 0 none, 1 sum partials -> norm and renorm scale of `slot`
+        size_t slot;
     };
     std::vector<Launch> launches;            // filled by prepare()
     int finish_prepared_host();             // bookkeeping after the launches ran
     int enqueue_prepared(hipStream_t s);     // launch everything prepare() built
     int enqueue_after(const Launch &l, hipStream_t s);  // the tail work of a launch (renorm sums)
     int enqueue_final(hipStream_t s);        // work after the last pass (final renorm, empty circuit)
+
+    // free every device buffer (state, checkpoints, plans, scratch); the next
+    // update re-simulates from scratch
+    void release_device();
+    // where the renormalisation sum of a launch with after == 1 goes
+    void sum_targets(const Launch &l, const double **partials, double **norm, double **scale) const {
+        *partials = d_partials_;
+        *norm = d_scalars_ + l.slot;
+        *scale = d_scalars_ + scalars_cap_ / 2 + l.slot;
+    }
+    int prep_mode() const { return prep_mode_; }
+    bool needs_final() const { return prep_S_ == 0 || (prep_renorm_ && prep_mode_ != 0); }
 
     void *state() const { return state_.p; }
     bool state_valid() const { return state_valid_; }
@@ -75,26 +93,47 @@ public:
     void dfree(void *p);
 
 private:
+    // A segment is a run of levels [lo, hi) that ends at an anchor level (the
+    // last segment ends at the end of the circuit).  Anchors are level ids:
+    // inserting a level only grows the segment it lands in, so the plans and
+    // checkpoints of the other segments stay usable.
+    struct Seg {
+        size_t lo = 0, hi = 0;
+        uint64_t anchor = 0;   // id of level hi-1
+        uint64_t key = 0;      // ids and versions of the segment's levels
+        uint64_t hash = 0;     // content hash (plan cache key)
+    };
+    struct Ckpt {
+        DevBuf buf;
+        bool valid = false;
+    };
     int K() const { return opts.ckpt_interval; }
     size_t num_segments() const { return (circ.num_levels() + size_t(K()) - 1) / size_t(K()); }
     bool stores_ckpt(size_t j, size_t S) const;
-    std::vector<LGate> segment_ops(size_t s) const;
+    std::vector<LGate> level_ops(size_t lo, size_t hi) const;
+    void build_segments(const PlanParams &pp);
+    size_t slot_of(uint64_t anchor);
     int ensure_state();
-    int ensure_ckpt(size_t j);
+    int ensure_scalars(size_t slots);
     int upload_plan(SegmentPlan &sp);
-    int try_closed(size_t s0, size_t s_edit, const std::vector<SegmentPlan> &old_plans, BlockSet &S);
-    int build_tile_lists(const BlockSet &S, size_t s0);
+    int try_closed(size_t s0, size_t s_edit, BlockSet &S);
 
     DevBuf state_;
-    std::vector<DevBuf> ckpt_;            // index j = boundary j (state after j*K levels)
-    std::vector<uint8_t> ckpt_valid_;
-    std::vector<SegmentPlan> plans_;
+    std::vector<Seg> segs_;
+    std::vector<SegmentPlan *> plans_;                    // plan of segs_[s]
+    std::unordered_map<uint64_t, SegmentPlan> plan_cache_;  // by content hash
+    std::unordered_map<uint64_t, uint64_t> key_hash_;       // segment key -> content hash
+    std::vector<uint64_t> prev_hashes_;                   // segment hashes at the last update
+    std::unordered_set<uint64_t> anchors_;
+    std::unordered_map<uint64_t, Ckpt> ckpts_;            // by anchor level id
+    std::unordered_map<uint64_t, size_t> slots_;          // anchor -> norm/scale slot (0: circuit end)
+    size_t next_slot_ = 1;
     bool state_valid_ = false;
     bool have_result_ = false;
 
     // device scratch
     double *d_partials_ = nullptr;  size_t partials_cap_ = 0;
-    double *d_scalars_ = nullptr;   size_t scalars_cap_ = 0;  // norms[j], scales[j] per boundary
+    double *d_scalars_ = nullptr;   size_t scalars_cap_ = 0;  // norms[slot], then scales[slot]
     unsigned long long *d_u64_ = nullptr;  size_t u64_cap_ = 0;
     uint64_t *d_mask_ = nullptr;    size_t mask_cap_ = 0;
     uint32_t *d_tiles_ = nullptr;   size_t tiles_cap_ = 0;
@@ -103,7 +142,7 @@ private:
     bool tuned_ = false;
 
     // prepared replay
-    size_t prep_s0_ = 0, prep_S_ = 0;
+    size_t prep_s0_ = 0, prep_S_ = 0, prep_first_edit_ = 0;
     int prep_mode_ = 0;
     bool prep_renorm_ = false;
     BlockSet prep_set_;

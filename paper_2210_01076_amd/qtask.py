@@ -282,6 +282,113 @@ def qtask_copy_bandwidth(device: int = 0, nbytes: int = 1 << 30, iters: int = 20
     return v.value
 
 
+# ----------------------------------------------------------------- serving
+
+def qtask_server_opts_default(**overrides) -> qtask_server_opts:
+    o = qtask_server_opts()
+    check(load().qtask_server_opts_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def qtask_server_create(opts: Optional[qtask_server_opts] = None) -> int:
+    s = vp()
+    check(load().qtask_server_create(ctypes.byref(opts) if opts is not None else None, ctypes.byref(s)),
+          "qtask_server_create")
+    return s.value
+
+
+def qtask_server_destroy(s) -> None:
+    check(load().qtask_server_destroy(s), "qtask_server_destroy")
+
+
+def qtask_server_open(s, n: int, dtype: int, opts: Optional[qtask_opts], nets) -> int:
+    """Open a session whose circuit is ``nets`` (lists of (kind, qubits, params))."""
+    kinds, qubits, nq, params, level_of = [], [], [], [], []
+    for li, net in enumerate(nets):
+        for kind, qs, ps in net:
+            kinds.append(KIND[kind] if isinstance(kind, str) else int(kind))
+            qubits.extend(list(qs) + [-1] * (3 - len(qs)))
+            nq.append(len(qs))
+            params.extend(list(ps) + [0.0] * (3 - len(ps)))
+            level_of.append(li)
+    g = len(kinds)
+    out = i32()
+    check(load().qtask_server_open(
+        s, n, dtype, ctypes.byref(opts) if opts is not None else None, len(nets), g,
+        (i32 * max(1, g))(*kinds), (i32 * max(3, 3 * g))(*qubits), (i32 * max(1, g))(*nq),
+        (ctypes.c_double * max(3, 3 * g))(*params), (u64 * max(1, g))(*level_of), ctypes.byref(out)),
+        "qtask_server_open")
+    return out.value
+
+
+def make_edits(e) -> List[qtask_edit]:
+    """C edit records of a ``workloads.Edit`` (positions refer to the current circuit)."""
+    out = []
+    if e.op == "insert":
+        li = e.net
+        if e.new_net:
+            out.append(qtask_edit(op=2, level=e.net))
+            li = e.net + 1
+        kind, qs, ps = e.gate
+        c = qtask_edit(op=0, kind=KIND[kind] if isinstance(kind, str) else int(kind), level=li, nq=len(qs),
+                       np=len(ps))
+        for j, q in enumerate(qs):
+            c.qubits[j] = q
+        for j, v in enumerate(ps):
+            c.params[j] = v
+        out.append(c)
+    elif e.op == "remove":
+        out.append(qtask_edit(op=1, level=e.net, gate_index=e.pos))
+    else:
+        raise ValueError(e.op)
+    return out
+
+
+def qtask_server_submit(s, session: int, edits: Sequence[qtask_edit]) -> int:
+    arr = (qtask_edit * max(1, len(edits)))(*edits)
+    t = u64()
+    check(load().qtask_server_submit(s, session, arr, len(edits), ctypes.byref(t)), "qtask_server_submit")
+    return t.value
+
+
+def _result(r: qtask_result) -> dict:
+    return {"ticket": r.ticket, "status": r.status, "session": r.session, "submit_ms": r.submit_ms,
+            "start_ms": r.start_ms, "done_ms": r.done_ms, "latency_ms": r.latency_ms,
+            "state_hash": r.state_hash, "stats": r.stats.as_dict()}
+
+
+def qtask_server_wait(s, ticket: int, timeout_ms: float = -1.0) -> dict:
+    r = qtask_result()
+    check(load().qtask_server_wait(s, ticket, timeout_ms, ctypes.byref(r)), "qtask_server_wait")
+    return _result(r)
+
+
+def qtask_server_poll(s, ticket: int) -> Optional[dict]:
+    r = qtask_result()
+    done = ctypes.c_int(0)
+    check(load().qtask_server_poll(s, ticket, ctypes.byref(done), ctypes.byref(r)), "qtask_server_poll")
+    return _result(r) if done.value else None
+
+
+def qtask_server_drain(s) -> None:
+    check(load().qtask_server_drain(s), "qtask_server_drain")
+
+
+def qtask_server_session(s, session: int) -> int:
+    h = vp()
+    check(load().qtask_server_session(s, session, ctypes.byref(h)), "qtask_server_session")
+    return h.value
+
+
+def qtask_server_usage(s):
+    b = u64()
+    r = i32()
+    check(load().qtask_server_usage(s, ctypes.byref(b), ctypes.byref(r)), "qtask_server_usage")
+    return b.value, r.value
+
+
 # ------------------------------------------------------------- convenience
 
 class Simulator:

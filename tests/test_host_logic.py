@@ -289,3 +289,29 @@ def test_tracker_sound_against_oracle(seed):
                         assert oracle.changed_blocks(a[lv], b[lv], bb) <= dirty, (trial, lv)
             else:
                 assert st["mode"] == 2
+
+
+def test_server_opts_and_edit_records():
+    o = Q.qtask_server_opts_default()
+    assert o.struct_size == Q.ctypes.sizeof(Q.qtask_server_opts)
+    assert o.budget_bytes == 256 << 30 and o.small_qubits == 16 and o.max_inflight >= 1 and o.use_graph == 1
+    ins = W.Edit(op="insert", net=3, gate=("cp", (1, 4), (0.5,)), new_net=True)
+    recs = Q.make_edits(ins)
+    assert [r.op for r in recs] == [2, 0]
+    assert recs[0].level == 3 and recs[1].level == 4
+    assert recs[1].kind == Q.KIND["cp"] and recs[1].nq == 2 and list(recs[1].qubits)[:2] == [1, 4]
+    assert recs[1].np == 1 and recs[1].params[0] == 0.5
+    rem = Q.make_edits(W.Edit(op="remove", net=7, pos=2))
+    assert len(rem) == 1 and rem[0].op == 1 and rem[0].level == 7 and rem[0].gate_index == 2
+
+
+def test_server_needs_a_device():
+    if Q.qtask_device_count() > 0:
+        pytest.skip("a device is present")
+    with pytest.raises(Q.QtaskError) as ei:
+        Q.qtask_server_create()
+    assert ei.value.code == Q.QTASK_E_DEVICE
+    bad = Q.qtask_server_opts_default(max_inflight=0)
+    with pytest.raises(Q.QtaskError) as ei:
+        Q.qtask_server_create(bad)
+    assert ei.value.code == Q.QTASK_E_ARG
