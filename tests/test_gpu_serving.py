@@ -13,15 +13,15 @@ from tests.gpu_util import bytes_equal, check_state, log
 pytestmark = pytest.mark.gpu
 
 
-def _specs(seed, count, n_lo, n_hi, depth, requests):
+def _specs(seed, count, n_lo, n_hi, depth, requests, dtype=None):
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
         n = int(rng.integers(n_lo, n_hi + 1))
-        dtype = "c128" if i % 2 == 0 else "c64"
+        dt = dtype or ("c128" if i % 2 == 0 else "c64")
         nets = W.layered_circuit(n, depth, seed + i)
         reqs = W.modifier_batches(n, nets, seed + 1000 + i, requests, 1, 3, W.LAYERED_EDIT_KINDS)
-        out.append((n, dtype, nets, reqs))
+        out.append((n, dt, nets, reqs))
     return out
 
 
@@ -113,7 +113,7 @@ def test_admission_evicts_and_restores():
     finishes, sessions evicted in the first phase are re-simulated from the
     start by their requests of the second, and every result equals the run
     alone."""
-    specs = _specs(99, 4, 18, 18, 8, 3)
+    specs = _specs(99, 4, 18, 18, 8, 3, dtype="c128")
     opts = dict(ckpt_interval=100)
     alone = [_alone(n, d, nets, reqs, opts) for n, d, nets, reqs in specs]
     state_bytes = (1 << 18) * 16
