@@ -21,6 +21,15 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
              # packed FP32 instructions are kept out of the generated code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # the op switch of the pass kernel branches on wave-uniform
+             # values only: keeping it a plain switch (instead of a chain of
+             # structured flow blocks) lets every case update the amplitude
+             # registers in place
+             "-mllvm", "-structurizecfg-skip-uniform-regions",
+             # FP64 multiply-adds as three-address v_fma_f64: the two-address
+             # v_fmac form ties the result to the addend's register, which
+             # forces copies wherever an op updates an amplitude in place
+             "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
              "-Wall", "-Wno-unused-function"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__=1",
              "-I" + os.path.join(ROCM, "include"), "-Wall", "-Wextra", "-Wno-unused-parameter"]

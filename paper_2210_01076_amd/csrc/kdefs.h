@@ -11,7 +11,9 @@
 // swizzled slot phys(l) (a GF(2)-linear map of the tile index l, so every
 // offset below is an XOR of per-bit contributions).  A stage maps QK_G tile
 // bits onto the QK_NREG registers of each thread and the other b-QK_G tile
-// bits onto the thread index; its ops then run on registers.
+// bits onto the thread index; its ops then run on registers.  Register i of
+// a thread sits at the XOR (LDS slot) or OR (global offset) of the
+// contributions of the set bits of i.
 #pragma once
 #include <stdint.h>
 
@@ -29,11 +31,12 @@ enum KOpType : uint8_t {
     KOP_D1 = 2,    // diagonal on bit a                          coef: d0 d1 (4)
     KOP_A1 = 3,    // anti-diagonal on bit a                     coef: m01 m10 (4)
     KOP_X1 = 4,    // exact exchange on bit a                    coef: none
-    KOP_CU = 5,    // dense 2x2 on bit b where bit a = 1         coef: 8
+    // 5: unused
     KOP_CX = 6,    // exact exchange on bit b where bit a = 1    coef: none
-    KOP_D2 = 7,    // diagonal on (a,b), local 2*bit(a)+bit(b)   coef: d0..d3 (8)
+    // 7: unused
     KOP_SWAP = 8,  // exact exchange of bits a and b             coef: none
-    KOP_U2 = 9,    // dense 4x4 on (a,b), local 2*bit(a)+bit(b)  coef: 32
+    // 9: unused (two-qubit gates are exchanges or phases; stages with many
+    //    ops become KOP_DENSE)
     KOP_CCX = 10,  // exact exchange on bit c where a = b = 1    coef: none
     KOP_DENSE = 11,// dense 16x16 on all QK_G register bits      coef: 512
     KOP_UR = 12,   // real 2x2 on bit a (H, RY)                 coef: m00 m01 m10 m11 (4 reals)
@@ -53,9 +56,9 @@ struct KOp {
 };
 
 struct KStage {
-    uint32_t reg_off[QK_NREG];        // LDS slot of register i relative to the thread base
+    uint32_t reg_bit[QK_G];           // LDS slot contribution of register-index bit j
     uint32_t thr_off[QK_MAX_THR_BITS];// LDS slot contribution of thread-index bit k
-    uint64_t g_reg[QK_NREG];          // first/last stage: global offset of register i
+    uint64_t g_bit[QK_G];             // first/last stage: global offset of register-index bit j
     uint64_t g_thr[QK_MAX_THR_BITS];  // first/last stage: global offset of thread-index bit k
     uint32_t op_begin, op_count;
     uint32_t kind;                    // KStageKind

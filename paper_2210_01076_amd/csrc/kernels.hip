@@ -31,6 +31,39 @@ template <> struct V2<float> { using T = float2; };
 #define NR QK_NREG
 
 // ------------------------------------------------------------ register ops
+// Every op updates its registers in place: the products that need an old
+// value are formed before the fused multiply-add that overwrites it, so the
+// register allocator can keep each amplitude in one register across the op
+// loop (no copies at the join of the op switch).  The two amplitudes of a
+// pair are updated by the same expression shape, out = fma(diag, own,
+// offdiag * other), whichever of them is the 0-side of the qubit.
+
+// fused multiply-add in the state's precision
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// (xr, xi) <- m * (xr, xi) for complex m (a phase or diagonal entry)
+template <typename R>
+__device__ __forceinline__ void cmul_in_place(R &xr, R &xi, R mr, R mi) {
+    const R t = mi * xi, u = mi * xr;
+    xr = fmaR(mr, xr, -t);
+    xi = fmaR(mr, xi, u);
+}
+
+// x <- a x + b y, y <- d y + c x for complex a b c d
+template <typename R>
+__device__ __forceinline__ void pair_u(R &xr, R &xi, R &yr, R &yi, R ar, R ai, R br, R bi, R cr, R ci, R dr,
+                                       R di) {
+    const R pr = fmaR(br, yr, -(bi * yi)), pi = fmaR(br, yi, bi * yr);  // b y
+    const R qr = fmaR(cr, xr, -(ci * xi)), qi = fmaR(cr, xi, ci * xr);  // c x
+    const R sx = fmaR(-ai, xi, pr), tx = fmaR(ai, xr, pi);
+    xr = fmaR(ar, xr, sx);
+    xi = fmaR(ar, xi, tx);
+    const R sy = fmaR(-di, yi, qr), ty = fmaR(di, yr, qi);
+    yr = fmaR(dr, yr, sy);
+    yi = fmaR(dr, yi, ty);
+}
+
 template <int A, typename R>
 __device__ __forceinline__ void op_u1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
     const R m00r = c[0], m00i = c[1], m01r = c[2], m01i = c[3];
@@ -39,11 +72,7 @@ __device__ __forceinline__ void op_u1(R (&re)[NR], R (&im)[NR], const R *__restr
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
-        re[i] = m00r * xr - m00i * xi + m01r * yr - m01i * yi;
-        im[i] = m00r * xi + m00i * xr + m01r * yi + m01i * yr;
-        re[j] = m10r * xr - m10i * xi + m11r * yr - m11i * yi;
-        im[j] = m10r * xi + m10i * xr + m11r * yi + m11i * yr;
+        pair_u(re[i], im[i], re[j], im[j], m00r, m00i, m01r, m01i, m10r, m10i, m11r, m11i);
     }
 }
 
@@ -52,12 +81,29 @@ __device__ __forceinline__ void op_d1(R (&re)[NR], R (&im)[NR], const R *__restr
     const R d0r = c[0], d0i = c[1], d1r = c[2], d1i = c[3];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const R dr = (i & (1 << A)) ? d1r : d0r;
-        const R di = (i & (1 << A)) ? d1i : d0i;
-        const R xr = re[i], xi = im[i];
-        re[i] = dr * xr - di * xi;
-        im[i] = dr * xi + di * xr;
+        if (i & (1 << A)) cmul_in_place(re[i], im[i], d1r, d1i);
+        else cmul_in_place(re[i], im[i], d0r, d0i);
     }
+}
+
+// Exchange two registers in place (v_swap_b32 on each 32-bit half): the
+// values keep their registers, so the op switch joins without copies.
+__device__ __forceinline__ void xchg(float &a, float &b) {
+    asm volatile("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void xchg(double &a, double &b) {
+    uint32_t al = __builtin_bit_cast(uint2, a).x, ah = __builtin_bit_cast(uint2, a).y;
+    uint32_t bl = __builtin_bit_cast(uint2, b).x, bh = __builtin_bit_cast(uint2, b).y;
+    asm volatile("v_swap_b32 %0, %1" : "+v"(al), "+v"(bl));
+    asm volatile("v_swap_b32 %0, %1" : "+v"(ah), "+v"(bh));
+    a = __builtin_bit_cast(double, make_uint2(al, ah));
+    b = __builtin_bit_cast(double, make_uint2(bl, bh));
+}
+
+template <typename R>
+__device__ __forceinline__ void swap_amp(R (&re)[NR], R (&im)[NR], int i, int j) {
+    xchg(re[i], re[j]);
+    xchg(im[i], im[j]);
 }
 
 template <int A, typename R>
@@ -67,19 +113,11 @@ __device__ __forceinline__ void op_a1(R (&re)[NR], R (&im)[NR], const R *__restr
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
-        re[i] = ar * yr - ai * yi;
-        im[i] = ar * yi + ai * yr;
-        re[j] = br * xr - bi * xi;
-        im[j] = br * xi + bi * xr;
+        xchg(re[i], re[j]);
+        xchg(im[i], im[j]);
+        cmul_in_place(re[i], im[i], ar, ai);
+        cmul_in_place(re[j], im[j], br, bi);
     }
-}
-
-template <typename R>
-__device__ __forceinline__ void swap_amp(R (&re)[NR], R (&im)[NR], int i, int j) {
-    const R tr = re[i], ti = im[i];
-    re[i] = re[j]; im[i] = im[j];
-    re[j] = tr; im[j] = ti;
 }
 
 template <int A, typename R>
@@ -90,22 +128,6 @@ __device__ __forceinline__ void op_x1(R (&re)[NR], R (&im)[NR], const R *__restr
 }
 
 template <int A, int B, typename R>
-__device__ __forceinline__ void op_cu(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
-    const R m00r = c[0], m00i = c[1], m01r = c[2], m01i = c[3];
-    const R m10r = c[4], m10i = c[5], m11r = c[6], m11i = c[7];
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if (!(i & (1 << A)) || (i & (1 << B))) continue;
-        const int j = i | (1 << B);
-        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
-        re[i] = m00r * xr - m00i * xi + m01r * yr - m01i * yi;
-        im[i] = m00r * xi + m00i * xr + m01r * yi + m01i * yr;
-        re[j] = m10r * xr - m10i * xi + m11r * yr - m11i * yi;
-        im[j] = m10r * xi + m10i * xr + m11r * yi + m11i * yr;
-    }
-}
-
-template <int A, int B, typename R>
 __device__ __forceinline__ void op_cx(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
@@ -113,48 +135,10 @@ __device__ __forceinline__ void op_cx(R (&re)[NR], R (&im)[NR], const R *__restr
 }
 
 template <int A, int B, typename R>
-__device__ __forceinline__ void op_d2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
-    R dr[4], di[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) { dr[l] = c[2 * l]; di[l] = c[2 * l + 1]; }
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const int l = (((i >> A) & 1) << 1) | ((i >> B) & 1);
-        const R xr = re[i], xi = im[i];
-        re[i] = dr[l] * xr - di[l] * xi;
-        im[i] = dr[l] * xi + di[l] * xr;
-    }
-}
-
-template <int A, int B, typename R>
 __device__ __forceinline__ void op_swap(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
         if ((i & (1 << A)) && !(i & (1 << B))) swap_amp(re, im, i, (i & ~(1 << A)) | (1 << B));
-}
-
-template <int A, int B, typename R>
-__device__ __forceinline__ void op_u2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if ((i & (1 << A)) || (i & (1 << B))) continue;
-        const int idx[4] = {i, i | (1 << B), i | (1 << A), i | (1 << A) | (1 << B)};
-        R xr[4], xi[4];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) { xr[l] = re[idx[l]]; xi[l] = im[idx[l]]; }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            R sr = 0, si = 0;
-#pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const R mr = c[2 * (4 * r + l)], mi = c[2 * (4 * r + l) + 1];
-                sr += mr * xr[l] - mi * xi[l];
-                si += mr * xi[l] + mi * xr[l];
-            }
-            re[idx[r]] = sr;
-            im[idx[r]] = si;
-        }
-    }
 }
 
 template <int A, int B, int C, typename R>
@@ -171,12 +155,16 @@ __device__ __forceinline__ void op_dense(R (&re)[NR], R (&im)[NR], const R *__re
     for (int i = 0; i < NR; ++i) { xr[i] = re[i]; xi[i] = im[i]; }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        R sr = 0, si = 0;
+        R sr = c[2 * NR * r] * xr[0], si = c[2 * NR * r] * xi[0];
+        sr = fmaR(-c[2 * NR * r + 1], xi[0], sr);
+        si = fmaR(c[2 * NR * r + 1], xr[0], si);
 #pragma unroll
-        for (int l = 0; l < NR; ++l) {
+        for (int l = 1; l < NR; ++l) {
             const R mr = c[2 * (NR * r + l)], mi = c[2 * (NR * r + l) + 1];
-            sr += mr * xr[l] - mi * xi[l];
-            si += mr * xi[l] + mi * xr[l];
+            sr = fmaR(mr, xr[l], sr);
+            sr = fmaR(-mi, xi[l], sr);
+            si = fmaR(mr, xi[l], si);
+            si = fmaR(mi, xr[l], si);
         }
         re[r] = sr;
         im[r] = si;
@@ -190,11 +178,12 @@ __device__ __forceinline__ void op_ur(R (&re)[NR], R (&im)[NR], const R *__restr
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
-        re[i] = m00 * xr + m01 * yr;
-        im[i] = m00 * xi + m01 * yi;
-        re[j] = m10 * xr + m11 * yr;
-        im[j] = m10 * xi + m11 * yi;
+        const R pr = m01 * re[j], qr = m10 * re[i];
+        re[i] = fmaR(m00, re[i], pr);
+        re[j] = fmaR(m11, re[j], qr);
+        const R pi = m01 * im[j], qi = m10 * im[i];
+        im[i] = fmaR(m00, im[i], pi);
+        im[j] = fmaR(m11, im[j], qi);
     }
 }
 
@@ -206,11 +195,11 @@ __device__ __forceinline__ void op_ux(R (&re)[NR], R (&im)[NR], const R *__restr
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        const R xr = re[i], xi = im[i], yr = re[j], yi = im[j];
-        re[i] = a * xr - b * yi;
-        im[i] = a * xi + b * yr;
-        re[j] = d * yr - cc * xi;
-        im[j] = d * yi + cc * xr;
+        const R p1 = b * im[j], p2 = b * re[j], q1 = cc * im[i], q2 = cc * re[i];
+        re[i] = fmaR(a, re[i], -p1);
+        im[i] = fmaR(a, im[i], p2);
+        re[j] = fmaR(d, re[j], -q1);
+        im[j] = fmaR(d, im[j], q2);
     }
 }
 
@@ -218,24 +207,16 @@ template <int A, typename R>
 __device__ __forceinline__ void op_p1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
     const R pr = c[0], pi = c[1];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if (!(i & (1 << A))) continue;
-        const R xr = re[i], xi = im[i];
-        re[i] = pr * xr - pi * xi;
-        im[i] = pr * xi + pi * xr;
-    }
+    for (int i = 0; i < NR; ++i)
+        if (i & (1 << A)) cmul_in_place(re[i], im[i], pr, pi);
 }
 
 template <int A, int B, typename R>
 __device__ __forceinline__ void op_p2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
     const R pr = c[0], pi = c[1];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if (!(i & (1 << A)) || !(i & (1 << B))) continue;
-        const R xr = re[i], xi = im[i];
-        re[i] = pr * xr - pi * xi;
-        im[i] = pr * xi + pi * xr;
-    }
+    for (int i = 0; i < NR; ++i)
+        if ((i & (1 << A)) && (i & (1 << B))) cmul_in_place(re[i], im[i], pr, pi);
 }
 
 #define SW1(F)                                   \
@@ -288,11 +269,8 @@ __device__ __forceinline__ void apply_op(const KOp op, R (&re)[NR], R (&im)[NR],
     case KOP_D1: SW1(op_d1) break;
     case KOP_A1: SW1(op_a1) break;
     case KOP_X1: SW1(op_x1) break;
-    case KOP_CU: SW2(op_cu) break;
     case KOP_CX: SW2(op_cx) break;
-    case KOP_D2: SW2(op_d2) break;
     case KOP_SWAP: SW2(op_swap) break;
-    case KOP_U2: SW2(op_u2) break;
     case KOP_CCX: SW3(op_ccx) break;
     case KOP_DENSE: op_dense(re, im, c); break;
     case KOP_UR: SW1(op_ur) break;
@@ -352,6 +330,30 @@ __device__ __forceinline__ uint32_t thr_lds(const KStage *__restrict__ S, uint32
     for (uint32_t k = 0; k < n_thr; ++k)
         if ((t >> k) & 1u) o ^= S->thr_off[k];
     return o;
+}
+
+// Per-register LDS slots (XOR) and global offsets (OR) from the per-bit
+// contributions; each register adds one bit to an earlier one.
+__device__ __forceinline__ void reg_slots(const KStage *__restrict__ S, uint32_t bt, uint32_t (&sl)[NR]) {
+    const uint32_t b0 = S->reg_bit[0], b1 = S->reg_bit[1], b2 = S->reg_bit[2], b3 = S->reg_bit[3];
+    sl[0] = bt;
+#pragma unroll
+    for (int i = 1; i < NR; ++i) {
+        const int low = i & -i;
+        const uint32_t bb = low == 1 ? b0 : low == 2 ? b1 : low == 4 ? b2 : b3;
+        sl[i] = sl[i & (i - 1)] ^ bb;
+    }
+}
+
+__device__ __forceinline__ void reg_goffs(const KStage *__restrict__ S, uint64_t g0, uint64_t (&g)[NR]) {
+    const uint64_t b0 = S->g_bit[0], b1 = S->g_bit[1], b2 = S->g_bit[2], b3 = S->g_bit[3];
+    g[0] = g0;
+#pragma unroll
+    for (int i = 1; i < NR; ++i) {
+        const int low = i & -i;
+        const uint64_t bb = low == 1 ? b0 : low == 2 ? b1 : low == 4 ? b2 : b3;
+        g[i] = g[i & (i - 1)] | bb;
+    }
 }
 
 template <typename R>
@@ -462,12 +464,12 @@ __device__ __forceinline__ void mfma_stage(const KStage *__restrict__ S, const R
     }
 }
 
-// One tile: the first stage's registers come straight from global memory,
-// the middle stages go through LDS, the last stage's registers go straight
-// back to global memory.
+// One tile (number idx of the pass, or tile_list[idx]).  The first stage's
+// registers come straight from global memory, the middle stages go through
+// LDS, the last stage's registers go straight back to global memory.
 template <typename R, bool MF>
-__device__ __forceinline__ void pass_body(uint32_t tile, uint32_t part_idx, void *dst_, const void *src_,
-                                          void *ckpt_, const KPass *__restrict__ P,
+__device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restrict__ tile_list, void *dst_,
+                                          const void *src_, void *ckpt_, const KPass *__restrict__ P,
                                           const KStage *__restrict__ stages, const KOp *__restrict__ ops,
                                           const R *__restrict__ coefs, const uint64_t *__restrict__ store_mask,
                                           const double *__restrict__ scale, double *__restrict__ partials,
@@ -475,110 +477,118 @@ __device__ __forceinline__ void pass_body(uint32_t tile, uint32_t part_idx, void
                                           typename V2<R>::T *__restrict__ lds) {
     using C = typename V2<R>::T;
     const uint32_t t = threadIdx.x;
-    uint64_t base = 0;
-    const uint32_t n_nonq = P->n_nonq;
-    for (uint32_t k = 0; k < n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
     const uint32_t n_thr = P->n_thr;
     const uint32_t ns = P->stage_count;
     const KStage *__restrict__ S0 = stages + P->stage_begin;
     const KStage *__restrict__ SL = S0 + (ns - 1);
+    const uint32_t tile = tile_list ? tile_list[idx] : idx;
+    uint64_t base = 0;
+    for (uint32_t k = 0; k < P->n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
 
+    // One loop over the stages with a single op-loop site: stage 0 gathers
+    // from global memory, the others from LDS; every stage but the last
+    // scatters back to LDS.  (One call site keeps the amplitude registers
+    // in place across the whole pass.)
     R re[NR], im[NR];
-    {
-        const uint64_t g0 = base | thr_glb<R>(S0, n_thr, t);
-        if (src_basis) {
+    for (uint32_t si = 0; si < ns; ++si) {
+        const KStage *__restrict__ S = S0 + si;
+        if (MF && S->kind == KSTAGE_MFMA) {
+            mfma_stage<R>(S, coefs, lds);
+            lds_barrier();
+            continue;
+        }
+        uint32_t sl[NR];
+        reg_slots(S, thr_lds<R>(S, n_thr, t), sl);
+        if (si == 0) {
+            uint64_t g[NR];
+            reg_goffs(S, base | thr_glb<R>(S, n_thr, t), g);
+            if (src_basis) {
 #pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                re[i] = (g0 | S0->g_reg[i]) == 0 ? R(1) : R(0);
-                im[i] = R(0);
+                for (int i = 0; i < NR; ++i) {
+                    re[i] = g[i] == 0 ? R(1) : R(0);
+                    im[i] = R(0);
+                }
+            } else {
+                const C *src = static_cast<const C *>(src_);
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const C y = src[g[i]];
+                    re[i] = y.x;
+                    im[i] = y.y;
+                }
+                if (scale) {
+                    const R sc = R(scale[0]);
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) { re[i] *= sc; im[i] *= sc; }
+                }
             }
         } else {
-            const C *src = static_cast<const C *>(src_);
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
-                const C y = src[g0 | S0->g_reg[i]];
+                const C y = lds[sl[i]];
                 re[i] = y.x;
                 im[i] = y.y;
             }
-            if (scale) {
-                const R sc = R(scale[0]);
-#pragma unroll
-                for (int i = 0; i < NR; ++i) { re[i] *= sc; im[i] *= sc; }
-            }
         }
-    }
-    run_ops<R>(S0, ops, coefs, re, im);
-    if (ns > 1) {
-        uint32_t bt = thr_lds<R>(S0, n_thr, t);
+        run_ops<R>(S, ops, coefs, re, im);
+        if (si + 1 == ns) break;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             C y;
             y.x = re[i];
             y.y = im[i];
-            lds[bt ^ S0->reg_off[i]] = y;
+            lds[sl[i]] = y;
         }
         lds_barrier();
-        for (uint32_t si = 1; si + 1 < ns; ++si) {
-            const KStage *__restrict__ S = S0 + si;
-            if (MF && S->kind == KSTAGE_MFMA) {
-                mfma_stage<R>(S, coefs, lds);
-            } else if (S->kind == KSTAGE_LIST) {
-                bt = thr_lds<R>(S, n_thr, t);
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    const C y = lds[bt ^ S->reg_off[i]];
-                    re[i] = y.x;
-                    im[i] = y.y;
-                }
-                run_ops<R>(S, ops, coefs, re, im);
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    C y;
-                    y.x = re[i];
-                    y.y = im[i];
-                    lds[bt ^ S->reg_off[i]] = y;
-                }
-            }
-            lds_barrier();
-        }
-        bt = thr_lds<R>(SL, n_thr, t);
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const C y = lds[bt ^ SL->reg_off[i]];
-            re[i] = y.x;
-            im[i] = y.y;
-        }
-        run_ops<R>(SL, ops, coefs, re, im);
     }
 
+    // store: plain (the common case), or only the blocks of the mask, and
+    // optionally the tile's squared norm; each option is a wave-uniform branch
     C *dst = static_cast<C *>(dst_);
     C *ck = static_cast<C *>(ckpt_);
-    const uint64_t gl = base | thr_glb<R>(SL, n_thr, t);
-    double acc = 0;
+    uint64_t g[NR];
+    reg_goffs(SL, base | thr_glb<R>(SL, n_thr, t), g);
+    if (!store_mask) {
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        C y;
-        y.x = re[i];
-        y.y = im[i];
-        const uint64_t idx = gl | SL->g_reg[i];
-        bool ok = true;
-        if (store_mask) {
-            const uint64_t blk = idx >> block_bits;
-            ok = (store_mask[blk >> 6] >> (blk & 63)) & 1;
+        for (int i = 0; i < NR; ++i) {
+            C y;
+            y.x = re[i];
+            y.y = im[i];
+            dst[g[i]] = y;
         }
-        if (ok) {
-            dst[idx] = y;
-            if (ck) ck[idx] = y;
+        if (ck) {
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                C y;
+                y.x = re[i];
+                y.y = im[i];
+                ck[g[i]] = y;
+            }
         }
-        if (partials) acc += double(y.x) * double(y.x) + double(y.y) * double(y.y);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            C y;
+            y.x = re[i];
+            y.y = im[i];
+            const uint64_t blk = g[i] >> block_bits;
+            if ((store_mask[blk >> 6] >> (blk & 63)) & 1) {
+                dst[g[i]] = y;
+                if (ck) ck[g[i]] = y;
+            }
+        }
     }
     if (partials) {
+        double acc = 0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) acc += double(re[i]) * double(re[i]) + double(im[i]) * double(im[i]);
         __shared__ double red[16];
         const double sum = block_sum(acc, red);
-        if (threadIdx.x == 0) partials[part_idx] = sum;
+        if (threadIdx.x == 0) partials[idx] = sum;
     }
 }
 
+// Pass kernel: one workgroup per tile.
 template <typename R, bool MF>
 __global__ void __launch_bounds__(512)
 qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, const KStage *__restrict__ stages,
@@ -587,8 +597,7 @@ qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, 
         uint32_t src_basis, uint32_t block_bits) {
     extern __shared__ __align__(16) unsigned char smem[];
     using C = typename V2<R>::T;
-    const uint32_t tile = tile_list ? tile_list[blockIdx.x] : blockIdx.x;
-    pass_body<R, MF>(tile, blockIdx.x, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale, partials,
+    pass_tile<R, MF>(blockIdx.x, tile_list, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale, partials,
                      src_basis, block_bits, reinterpret_cast<C *>(smem));
 }
 
@@ -615,10 +624,9 @@ qk_pass_batch(const KBatchItem *__restrict__ items, const uint32_t *__restrict__
     const uint32_t local = blockIdx.x - it->tile_begin;
     if (local >= it->n_tiles || it->threads != blockDim.x) return;
     const KArgs &a = it->args;
-    const uint32_t tile = a.tile_list ? a.tile_list[local] : local;
-    pass_body<R, false>(tile, local, a.dst, a.src, a.ckpt, a.pass, a.stages, a.ops,
-                        static_cast<const R *>(a.coefs), a.store_mask, a.scale, a.partials, a.src_basis,
-                        a.block_bits, reinterpret_cast<C *>(smem));
+    pass_tile<R, false>(local, a.tile_list, a.dst, a.src, a.ckpt, a.pass, a.stages,
+                         a.ops, static_cast<const R *>(a.coefs), a.store_mask, a.scale, a.partials, a.src_basis,
+                         a.block_bits, reinterpret_cast<C *>(smem));
 }
 
 // Batched renormalisation sums: workgroup i adds the per-tile partials of

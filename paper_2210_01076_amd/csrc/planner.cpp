@@ -342,12 +342,7 @@ void pack_blob(SegmentPlan &sp) {
             std::memset(&S, 0, sizeof(S));
             const int W = int(st.tbits.size());
             if (!st.mfma) {
-                for (int i = 0; i < QK_NREG; ++i) {
-                    uint64_t g = 0;
-                    for (int j = 0; j < G; ++j)
-                        if ((i >> j) & 1) g |= goff(st.tbits[j]);
-                    S.g_reg[i] = g;
-                }
+                for (int j = 0; j < G; ++j) S.g_bit[j] = goff(st.tbits[j]);
                 for (int j = 0; j < n_thr; ++j) S.g_thr[j] = goff(st.tpos[j]);
             }
             if (st.mfma) {
@@ -368,12 +363,7 @@ void pack_blob(SegmentPlan &sp) {
                 continue;
             }
             S.kind = KSTAGE_LIST;
-            for (int i = 0; i < QK_NREG; ++i) {
-                uint32_t o = 0;
-                for (int j = 0; j < G; ++j)
-                    if ((i >> j) & 1) o ^= phys(st.tbits[j]);
-                S.reg_off[i] = o;
-            }
+            for (int j = 0; j < G; ++j) S.reg_bit[j] = phys(st.tbits[j]);
             for (int j = 0; j < n_thr; ++j) S.thr_off[j] = phys(st.tpos[j]);
             S.op_begin = uint32_t(oi);
             auto reg_of = [&](int q) {
@@ -488,9 +478,15 @@ std::string validate_plan(const SegmentPlan &sp) {
                 for (int k = 0; k < n_thr; ++k)
                     if ((t >> k) & 1) gt |= S.g_thr[k];
                 for (int i = 0; i < QK_NREG; ++i) {
-                    if (gt & S.g_reg[i]) { err << "pass " << pi << ": global map overlap"; return err.str(); }
-                    offs.push_back(gt | S.g_reg[i]);
-                    gmask |= gt | S.g_reg[i];
+                    uint64_t gr = 0;
+                    for (int j = 0; j < G; ++j)
+                        if ((i >> j) & 1) {
+                            if (gr & S.g_bit[j]) { err << "pass " << pi << ": register bits overlap"; return err.str(); }
+                            gr |= S.g_bit[j];
+                        }
+                    if (gt & gr) { err << "pass " << pi << ": global map overlap"; return err.str(); }
+                    offs.push_back(gt | gr);
+                    gmask |= gt | gr;
                 }
             }
             std::sort(offs.begin(), offs.end());
@@ -517,7 +513,10 @@ std::string validate_plan(const SegmentPlan &sp) {
                     for (int k = 0; k < n_thr; ++k)
                         if ((t >> k) & 1) bt ^= S.thr_off[k];
                     for (int i = 0; i < QK_NREG; ++i) {
-                        const uint32_t sl = bt ^ S.reg_off[i];
+                        uint32_t ro = 0;
+                        for (int j = 0; j < G; ++j)
+                            if ((i >> j) & 1) ro ^= S.reg_bit[j];
+                        const uint32_t sl = bt ^ ro;
                         if (sl >= tile || seen2[sl]++) { err << "pass " << pi << " stage " << s << ": reg map"; return err.str(); }
                     }
                 }

@@ -87,7 +87,7 @@ void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std:
         for (int j = 0; j < 2; ++j)
             if (hb(g.q[j]) >= 0) need |= uint64_t(1) << hb(g.q[j]);
         break;
-    case KOP_CX: case KOP_CU:
+    case KOP_CX:
         if (hb(g.q[0]) >= 0) need |= uint64_t(1) << hb(g.q[0]);
         break;
     case KOP_CCX:
