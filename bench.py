@@ -287,7 +287,7 @@ def main():
         "c64": r64,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "qk_pass<double, false>", "bytes_per_launch": r128["pass_bytes"],
+                     "kernel": "qk_pass_pf<double>", "bytes_per_launch": r128["pass_bytes"],
                      "avg_launch_ms": r128["pass_avg_ms"],
                      "launch": {"grid": 1 << (wl.n - r128["tile_bits"]), "block": 1 << (r128["tile_bits"] - 4)}},
         "serving": serving,

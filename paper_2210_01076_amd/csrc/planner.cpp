@@ -313,7 +313,8 @@ void pack_blob(SegmentPlan &sp) {
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t bytes_pass = align(sp.passes.size() * sizeof(KPass));
     const size_t bytes_stage = align(n_stage * sizeof(KStage));
-    const size_t bytes_op = align(std::max<size_t>(n_op, 1) * sizeof(KOp));
+    // one spare record: the kernel reads the record after a stage's last op
+    const size_t bytes_op = align((n_op + 1) * sizeof(KOp));
     const size_t bytes_coef = align(std::max<size_t>(n_coef, 1) * sizeof(R));
     sp.off_stage = bytes_pass;
     sp.off_op = bytes_pass + bytes_stage;
