@@ -117,7 +117,7 @@ typedef struct qtask_stats {
     uint64_t levels_replayed;
     uint64_t segments_replayed;
     uint64_t first_level;      /* first level index re-simulated */
-    uint64_t passes;           /* pass kernels launched */
+    uint64_t passes;           /* pass kernels launched (passes with no tile to run are skipped) */
     uint64_t tiles;            /* tiles processed over all passes */
     uint64_t stages;           /* stages over all passes (per tile) */
     uint64_t dirty_blocks;     /* blocks in the affected set (mode 3), else all blocks */

@@ -638,9 +638,11 @@ int Session::prepare(bool force_full) {
             }
             flops += double(tiles) * double(uint64_t(1) << b) * pf;
             mfma_flops += double(tiles) * double(uint64_t(1) << b) * mf;
-            st.passes += 1;
+            if (tiles > 0) {
+                st.passes += 1;
+                st.stages += sp.passes[p].stages.size();
+            }
             st.tiles += tiles;
-            st.stages += sp.passes[p].stages.size();
         }
         st.gate_amp_updates += sp.n_gates * (uint64_t(1) << n);
     }

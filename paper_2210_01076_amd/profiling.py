@@ -5,7 +5,8 @@ csv``) and two counter directories (``--pmc FETCH_SIZE`` and ``--pmc
 WRITE_SIZE``, one pass each) of the same benchmark command, and writes
 
 * a short text summary: the kernel statistics, the average duration of the
-  full-simulation pass launches (selected by their grid and workgroup size),
+  pass launches of the benchmark's timed steps (the last N launches of the
+  kernel with the benchmark's workgroup size, N as the benchmark reports),
   and the HBM bytes per launch from the two counters, each scaled by what the
   same counter reads for the plain copy kernel of known size;
 * a JSON record of the traffic figures, keyed to a hash of the kernel source
@@ -15,7 +16,8 @@ WRITE_SIZE``, one pass each) of the same benchmark command, and writes
 Usage::
 
     python -m paper_2210_01076_amd.profiling --trace DIR --fetch DIR --write DIR \\
-        --bench-json FILE --copy-bytes N --out-txt FILE --out-json FILE --command "..."
+        --bench-json FILE --counter-bench-json FILE --out-txt FILE --out-json FILE \\
+        --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
 """
 from __future__ import annotations
 
@@ -57,58 +59,65 @@ def kernel_stats(trace_dir: str):
     return rows
 
 
-def dispatches(trace_dir: str, kernel: str):
-    """Durations (ns) of the kernel's dispatches, grouped by (grid, workgroup)."""
-    out = defaultdict(list)
+def dispatches(trace_dir: str, kernel: str, block: int):
+    """Durations (ns) of the kernel's dispatches with this workgroup size, in
+    dispatch order."""
+    rows = []
     with open(_one(trace_dir, "kernel_trace.csv")) as f:
         for r in csv.DictReader(f):
-            if _short(r["Kernel_Name"]) != kernel:
-                continue
-            key = (int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
-            out[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    return out
+            if _short(r["Kernel_Name"]) == kernel and int(r["Workgroup_Size_X"]) == block:
+                rows.append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    return [d for _, d in sorted(rows)]
 
 
 def counters(counter_dir: str, name: str):
-    """Counter values (KiB) per dispatch, grouped by (kernel, grid, workgroup)."""
-    out = defaultdict(list)
+    """Counter values (KiB) per dispatch in dispatch order, by (kernel, workgroup)."""
+    rows = defaultdict(list)
     with open(_one(counter_dir, "counter_collection.csv")) as f:
         for r in csv.DictReader(f):
             if r["Counter_Name"] != name:
                 continue
-            key = (_short(r["Kernel_Name"]), int(r["Grid_Size"]), int(r["Workgroup_Size"]))
-            out[key].append(float(r["Counter_Value"]))
-    return out
+            key = (_short(r["Kernel_Name"]), int(r["Workgroup_Size"]))
+            rows[key].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    return {k: [v for _, v in sorted(x)] for k, x in rows.items()}
 
 
 def _mean(xs):
     return sum(xs) / len(xs) if xs else float("nan")
 
 
-def summarize(trace, fetch, write, bench_json, copy_bytes, command, kernel, copy_kernel):
-    with open(bench_json) as f:
-        bench = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
+def _bench_line(path):
+    with open(path) as f:
+        return json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
+
+
+def summarize(trace, fetch, write, bench_json, counter_bench_json, copy_bytes, command, kernel, copy_kernel):
+    bench = _bench_line(bench_json)
+    cbench = _bench_line(counter_bench_json)
+    counter_launches = cbench["roofline"]["launches_timed"]
+    counter_alg = cbench["roofline"]["bytes_per_launch"]
     roof = bench["roofline"]
-    launch = roof["launch"]          # {"grid": workgroups, "block": threads}
-    grid_threads = launch["grid"] * launch["block"]
+    block, n_timed = roof["block"], roof["launches_timed"]
     stats = kernel_stats(trace)
-    d = dispatches(trace, kernel)
-    durs = d.get((grid_threads, launch["block"]), [])
+    durs = dispatches(trace, kernel, block)[-n_timed:]
     fc = counters(fetch, "FETCH_SIZE")
     wc = counters(write, "WRITE_SIZE")
-    key = (kernel, grid_threads, launch["block"])
+    key = (kernel, block)
     ckey = [k for k in fc if k[0] == copy_kernel]
     copy_f = _mean([v for k in ckey for v in fc[k]])
     copy_w = _mean([v for k in ckey for v in wc.get(k, [])])
     f_scale = (copy_bytes / 1024.0) / copy_f
     w_scale = (copy_bytes / 1024.0) / copy_w
-    f_kib = _mean(fc.get(key, []))
-    w_kib = _mean(wc.get(key, []))
+    # the counter runs use their own (shorter) benchmark command: their
+    # timed launches are the last ones of the kernel as well
+    n_cnt = counter_launches
+    f_kib = _mean(fc.get(key, [])[-n_cnt:])
+    w_kib = _mean(wc.get(key, [])[-n_cnt:])
     hbm = (f_kib * f_scale + w_kib * w_scale) * 1024.0
     rec = {
         "kernel": kernel,
         "workload": bench["config"]["workload"],
-        "launch": launch,
+        "block": block,
         "dispatches_traced": len(durs),
         "avg_duration_us": _mean(durs) / 1e3,
         "bench_avg_launch_ms": roof["avg_launch_ms"],
@@ -121,7 +130,8 @@ def summarize(trace, fetch, write, bench_json, copy_bytes, command, kernel, copy
         "fetch_scale": f_scale,
         "write_scale": w_scale,
         "hbm_bytes_per_launch": hbm,
-        "traffic_over_algorithmic": hbm / roof["bytes_per_launch"],
+        "counter_run_algorithmic_bytes_per_launch": counter_alg,
+        "traffic_over_algorithmic": hbm / counter_alg,
         "kernel_source_hash": kernel_source_hash(),
         "command": command,
     }
@@ -134,9 +144,8 @@ def summarize(trace, fetch, write, bench_json, copy_bytes, command, kernel, copy
         lines.append("%-44s %7d %12.2f %12.2f %6.2f" % (name[:44], calls, avg / 1e3, tot / 1e6, p))
     lines += [
         "",
-        "full-simulation pass launches (%d workgroups x %d threads): %d dispatches, avg %.2f us "
-        "(bench, HIP events: %.2f us)" % (launch["grid"], launch["block"], len(durs), rec["avg_duration_us"],
-                                         roof["avg_launch_ms"] * 1e3),
+        "timed pass launches (%d threads per workgroup): %d dispatches, avg %.2f us "
+        "(bench, HIP events: %.2f us)" % (block, len(durs), rec["avg_duration_us"], roof["avg_launch_ms"] * 1e3),
         "algorithmic bytes per launch: %.0f" % roof["bytes_per_launch"],
         "achieved (algorithmic / traced avg): %.1f GB/s" % (roof["bytes_per_launch"] / (rec["avg_duration_us"] * 1e3)),
         "",
@@ -144,7 +153,8 @@ def summarize(trace, fetch, write, bench_json, copy_bytes, command, kernel, copy
             f_kib, copy_f, copy_bytes, f_scale),
         "WRITE_SIZE: %.1f KiB/launch; copy kernel %.1f KiB for %d bytes written -> scale %.4f" % (
             w_kib, copy_w, copy_bytes, w_scale),
-        "HBM bytes per launch (scaled): %.0f = %.3f x algorithmic" % (hbm, rec["traffic_over_algorithmic"]),
+        "HBM bytes per launch (scaled): %.0f = %.3f x the algorithmic %.0f of the counter runs" % (
+            hbm, rec["traffic_over_algorithmic"], counter_alg),
         "kernel source hash: %s" % rec["kernel_source_hash"],
     ]
     return rec, "\n".join(lines) + "\n"
@@ -155,7 +165,8 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--bench-json", required=True)
+    ap.add_argument("--bench-json", required=True, help="output of the traced benchmark run")
+    ap.add_argument("--counter-bench-json", required=True, help="output of the counter benchmark runs")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--kernel", default="qk_pass_pf<double>")
     ap.add_argument("--copy-kernel", default="qk_copy")
@@ -166,7 +177,8 @@ def main():
     ap.add_argument("--out-json", required=True)
     a = ap.parse_args()
     command = {"trace": a.cmd_trace, "fetch": a.cmd_fetch, "write": a.cmd_write}
-    rec, txt = summarize(a.trace, a.fetch, a.write, a.bench_json, a.copy_bytes, command, a.kernel, a.copy_kernel)
+    rec, txt = summarize(a.trace, a.fetch, a.write, a.bench_json, a.counter_bench_json, a.copy_bytes, command,
+                         a.kernel, a.copy_kernel)
     with open(a.out_txt, "w") as f:
         f.write(txt)
     with open(a.out_json, "w") as f:
