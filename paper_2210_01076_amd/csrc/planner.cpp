@@ -134,20 +134,21 @@ struct Packer {
     const PlanParams &pp;
     explicit Packer(const PlanParams &p) : pp(p) {}
 
-    int tile_bit_of(const PPass &ps, int q) const {
-        for (size_t p = 0; p < ps.qlist.size(); ++p)
-            if (ps.qlist[p] == q) return int(p);
-        throw std::logic_error("qubit not in pass");
-    }
-
     // Build the stages of a pass from its ops (program order).
-    void pack_stages(PPass &ps, const std::vector<LGate> &ops) const {
+    void pack_stages(PPass &ps, const std::vector<const LGate *> &ops) const {
         const bool dense_mode = pp.fusion == QTASK_FUSE_DENSE;
         const int W = dense_mode ? std::min(pp.fuse_k, pp.b) : QK_G;
+        // tile bit of each pass qubit
+        int8_t tbit[64];
+        for (int q = 0; q < 64; ++q) tbit[q] = -1;
+        for (size_t p = 0; p < ps.qlist.size(); ++p) tbit[ps.qlist[p]] = int8_t(p);
         std::vector<uint32_t> tmask(ops.size());
         for (size_t i = 0; i < ops.size(); ++i) {
             uint32_t m = 0;
-            for (int j = 0; j < ops[i].nq; ++j) m |= 1u << tile_bit_of(ps, ops[i].q[j]);
+            for (int j = 0; j < ops[i]->nq; ++j) {
+                if (tbit[ops[i]->q[j]] < 0) throw std::logic_error("qubit not in pass");
+                m |= 1u << tbit[ops[i]->q[j]];
+            }
             tmask[i] = m;
         }
         std::vector<size_t> rem(ops.size());
@@ -183,10 +184,11 @@ struct Packer {
             st.tpos = lane_order(others, pp.swz);
             // ops, merging consecutive one-qubit gates on the same qubit
             std::vector<int> last(pp.b, -1);
+            st.ops.reserve(take.size());
             for (size_t idx : take) {
-                const LGate &g = ops[idx];
+                const LGate &g = *ops[idx];
                 if (mergeable(g)) {
-                    const int tb = tile_bit_of(ps, g.q[0]);
+                    const int tb = tbit[g.q[0]];
                     const int li = last[tb];
                     if (li >= 0 && mergeable(st.ops[li])) {
                         LGate mg = merge_1q(g, st.ops[li]);
@@ -197,7 +199,7 @@ struct Packer {
                     }
                 }
                 st.ops.push_back(g);
-                for (int j = 0; j < g.nq; ++j) last[tile_bit_of(ps, g.q[j])] = int(st.ops.size()) - 1;
+                for (int j = 0; j < g.nq; ++j) last[tbit[g.q[j]]] = int(st.ops.size()) - 1;
             }
             double fl = 0;
             for (const auto &g : st.ops) fl += g.flops_per_amp();
@@ -267,14 +269,20 @@ struct Packer {
         // every pass can take at least the first pending gate
         const int c = std::max(0, std::min(pp.c, pp.b - 3));
         const uint64_t low = (uint64_t(1) << c) - 1;
+        std::vector<uint64_t> mask(ops.size());
+        for (size_t i = 0; i < ops.size(); ++i) mask[i] = ops[i].mask();
         std::vector<size_t> rem(ops.size());
         for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
         std::vector<PPass> passes;
+        std::vector<size_t> take, left;
+        take.reserve(ops.size());
+        left.reserve(ops.size());
         while (!rem.empty()) {
             uint64_t Q = low, blocked = 0;
-            std::vector<size_t> take, left;
+            take.clear();
+            left.clear();
             for (size_t idx : rem) {
-                const uint64_t m = ops[idx].mask();
+                const uint64_t m = mask[idx];
                 if (m & blocked) { blocked |= m; left.push_back(idx); continue; }
                 if (popc(Q | m) <= pp.b) { Q |= m; take.push_back(idx); }
                 else { blocked |= m; left.push_back(idx); }
@@ -285,8 +293,9 @@ struct Packer {
             ps.qmask = Q;
             for (int q = 0; q < pp.n; ++q)
                 if ((Q >> q) & 1) ps.qlist.push_back(q);
-            std::vector<LGate> pops;
-            for (size_t idx : take) pops.push_back(ops[idx]);
+            std::vector<const LGate *> pops;
+            pops.reserve(take.size());
+            for (size_t idx : take) pops.push_back(&ops[idx]);
             ps.n_gates = int(pops.size());
             pack_stages(ps, pops);
             finish_pass(ps);
@@ -400,11 +409,6 @@ void pack_blob(SegmentPlan &sp) {
     }
 }
 
-uint64_t fnv(uint64_t h, const void *p, size_t n) {
-    const uint8_t *b = static_cast<const uint8_t *>(p);
-    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
-    return h;
-}
 
 }  // namespace
 
@@ -416,17 +420,32 @@ uint32_t lds_phys(uint32_t l, int swz) {
 }
 
 uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp) {
-    uint64_t h = 1469598103934665603ull;
-    h = fnv(h, &pp, sizeof(pp));
+    // 64-bit words through a splitmix finalizer (the plan cache is keyed by
+    // this value, so it mixes every bit of the kinds, qubits and matrices)
+    auto mix = [](uint64_t h, uint64_t w) {
+        uint64_t x = h + w * 0x9e3779b97f4a7c15ull;
+        x ^= x >> 30; x *= 0xbf58476d1ce4e5b9ull;
+        x ^= x >> 27; x *= 0x94d049bb133111ebull;
+        return x ^ (x >> 31);
+    };
+    uint64_t h = 0x243f6a8885a308d3ull;
+    const int64_t params[7] = {pp.n, pp.b, pp.c, pp.dtype, pp.fusion, pp.fuse_k, pp.swz};
+    for (int64_t v : params) h = mix(h, uint64_t(v));
     for (const auto &g : ops) {
-        h = fnv(h, &g.kop, sizeof(g.kop));
-        h = fnv(h, g.q, sizeof(g.q));
-        for (const cd &z : g.m) h = fnv(h, &z, sizeof(z));
+        h = mix(h, uint64_t(g.kop) | (uint64_t(uint8_t(g.nq)) << 8) | (uint64_t(uint16_t(g.q[0])) << 16) |
+                       (uint64_t(uint16_t(g.q[1])) << 32) | (uint64_t(uint16_t(g.q[2])) << 48));
+        for (const cd &z : g.m) {
+            uint64_t re, im;
+            const double r = z.real(), i = z.imag();
+            std::memcpy(&re, &r, 8);
+            std::memcpy(&im, &i, 8);
+            h = mix(mix(h, re), im);
+        }
     }
     return h;
 }
 
-SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp) {
+SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp, uint64_t hash) {
     if (pp.b < QK_MIN_TILE_BITS || pp.b > QK_MAX_TILE_BITS || pp.b > pp.n || pp.c < 0 || pp.c > pp.b)
         throw std::invalid_argument("plan parameters");
     SegmentPlan sp;
@@ -449,7 +468,7 @@ SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp) {
         for (const auto &st : ps.stages) sp.flops_per_amp += st.flops;
     if (pp.dtype == 0) pack_blob<double>(sp);
     else pack_blob<float>(sp);
-    sp.hash = segment_hash(ops, pp);
+    sp.hash = hash ? hash : segment_hash(ops, pp);
     return sp;
 }
 

@@ -51,8 +51,9 @@ struct SegmentPlan {
 };
 
 // Plan a segment.  `ops` are the lowered gates of the segment's levels in
-// canonical order (level by level; inside a level by lowest qubit).
-SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp);
+// canonical order (level by level; inside a level by lowest qubit).  `hash`
+// is segment_hash(ops, pp) when the caller has it (0: computed here).
+SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp, uint64_t hash = 0);
 
 // Hash of a segment's content and the parameters that shape its plan.
 uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp);

@@ -441,7 +441,7 @@ int Session::prepare(bool force_full) {
             if (!plan_cache_.count(sg.hash)) {
                 SegmentPlan np;
                 try {
-                    np = plan_segment(ops, pp);
+                    np = plan_segment(ops, pp, sg.hash);
                 } catch (const std::exception &e) {
                     last_error = e.what();
                     return QTASK_E_ARG;

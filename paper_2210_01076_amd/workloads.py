@@ -287,7 +287,7 @@ def config(cfg: int, *, levels: int = None, n: int = None, batches: int = None) 
         nets = layered_circuit(n, levels or 200, seed_for(2))
         b = modifier_batches(n, nets, seed_for(2, "modifier"), batches or 100, 1, 4,
                              LAYERED_EDIT_KINDS)
-        return Workload("layered_n%d_l%d" % (n, levels or 200), n, nets, b, ckpt_levels=100)
+        return Workload("layered_n%d_l%d" % (n, levels or 200), n, nets, b, ckpt_levels=50)
     if cfg == 3:
         n = n or 30
         nets = layered_circuit(n, levels or 300, seed_for(3))
