@@ -30,6 +30,9 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
              # v_fmac form ties the result to the addend's register, which
              # forces copies wherever an op updates an amplitude in place
              "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
+             # the same for FP32: v_fmac_f32 comes with the dl-insts feature
+             # (whose dot-product instructions the kernels do not use)
+             "-Xclang", "-target-feature", "-Xclang", "-dl-insts",
              "-Wall", "-Wno-unused-function"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__=1",
              "-I" + os.path.join(ROCM, "include"), "-Wall", "-Wextra", "-Wno-unused-parameter"]

@@ -65,24 +65,24 @@ __device__ __forceinline__ void pair_u(R &xr, R &xi, R &yr, R &yi, R ar, R ai, R
 }
 
 template <int A, typename R>
-__device__ __forceinline__ void op_u1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_u1(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     const R m00r = c[0], m00i = c[1], m01r = c[2], m01i = c[3];
     const R m10r = c[4], m10i = c[5], m11r = c[6], m11i = c[7];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        pair_u(re[i], im[i], re[j], im[j], m00r, m00i, m01r, m01i, m10r, m10i, m11r, m11i);
+        pair_u(a[i].x, a[i].y, a[j].x, a[j].y, m00r, m00i, m01r, m01i, m10r, m10i, m11r, m11i);
     }
 }
 
 template <int A, typename R>
-__device__ __forceinline__ void op_d1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_d1(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     const R d0r = c[0], d0i = c[1], d1r = c[2], d1i = c[3];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        if (i & (1 << A)) cmul_in_place(re[i], im[i], d1r, d1i);
-        else cmul_in_place(re[i], im[i], d0r, d0i);
+        if (i & (1 << A)) cmul_in_place(a[i].x, a[i].y, d1r, d1i);
+        else cmul_in_place(a[i].x, a[i].y, d0r, d0i);
     }
 }
 
@@ -101,58 +101,58 @@ __device__ __forceinline__ void xchg(double &a, double &b) {
 }
 
 template <typename R>
-__device__ __forceinline__ void swap_amp(R (&re)[NR], R (&im)[NR], int i, int j) {
-    xchg(re[i], re[j]);
-    xchg(im[i], im[j]);
+__device__ __forceinline__ void swap_amp(typename V2<R>::T (&a)[NR], int i, int j) {
+    xchg(a[i].x, a[j].x);
+    xchg(a[i].y, a[j].y);
 }
 
 template <int A, typename R>
-__device__ __forceinline__ void op_a1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_a1(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     const R ar = c[0], ai = c[1], br = c[2], bi = c[3];  // m01, m10
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        xchg(re[i], re[j]);
-        xchg(im[i], im[j]);
-        cmul_in_place(re[i], im[i], ar, ai);
-        cmul_in_place(re[j], im[j], br, bi);
+        xchg(a[i].x, a[j].x);
+        xchg(a[i].y, a[j].y);
+        cmul_in_place(a[i].x, a[i].y, ar, ai);
+        cmul_in_place(a[j].x, a[j].y, br, bi);
     }
 }
 
 template <int A, typename R>
-__device__ __forceinline__ void op_x1(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+__device__ __forceinline__ void op_x1(typename V2<R>::T (&a)[NR], const R *__restrict__) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-        if (!(i & (1 << A))) swap_amp(re, im, i, i | (1 << A));
+        if (!(i & (1 << A))) swap_amp<R>(a, i, i | (1 << A));
 }
 
 template <int A, int B, typename R>
-__device__ __forceinline__ void op_cx(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+__device__ __forceinline__ void op_cx(typename V2<R>::T (&a)[NR], const R *__restrict__) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-        if ((i & (1 << A)) && !(i & (1 << B))) swap_amp(re, im, i, i | (1 << B));
+        if ((i & (1 << A)) && !(i & (1 << B))) swap_amp<R>(a, i, i | (1 << B));
 }
 
 template <int A, int B, typename R>
-__device__ __forceinline__ void op_swap(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+__device__ __forceinline__ void op_swap(typename V2<R>::T (&a)[NR], const R *__restrict__) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-        if ((i & (1 << A)) && !(i & (1 << B))) swap_amp(re, im, i, (i & ~(1 << A)) | (1 << B));
+        if ((i & (1 << A)) && !(i & (1 << B))) swap_amp<R>(a, i, (i & ~(1 << A)) | (1 << B));
 }
 
 template <int A, int B, int C, typename R>
-__device__ __forceinline__ void op_ccx(R (&re)[NR], R (&im)[NR], const R *__restrict__) {
+__device__ __forceinline__ void op_ccx(typename V2<R>::T (&a)[NR], const R *__restrict__) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-        if ((i & (1 << A)) && (i & (1 << B)) && !(i & (1 << C))) swap_amp(re, im, i, i | (1 << C));
+        if ((i & (1 << A)) && (i & (1 << B)) && !(i & (1 << C))) swap_amp<R>(a, i, i | (1 << C));
 }
 
 template <typename R>
-__device__ __forceinline__ void op_dense(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_dense(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     R xr[NR], xi[NR];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) { xr[i] = re[i]; xi[i] = im[i]; }
+    for (int i = 0; i < NR; ++i) { xr[i] = a[i].x; xi[i] = a[i].y; }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         R sr = c[2 * NR * r] * xr[0], si = c[2 * NR * r] * xi[0];
@@ -166,104 +166,104 @@ __device__ __forceinline__ void op_dense(R (&re)[NR], R (&im)[NR], const R *__re
             si = fmaR(mr, xi[l], si);
             si = fmaR(mi, xr[l], si);
         }
-        re[r] = sr;
-        im[r] = si;
+        a[r].x = sr;
+        a[r].y = si;
     }
 }
 
 template <int A, typename R>
-__device__ __forceinline__ void op_ur(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_ur(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     const R m00 = c[0], m01 = c[1], m10 = c[2], m11 = c[3];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        const R pr = m01 * re[j], qr = m10 * re[i];
-        re[i] = fmaR(m00, re[i], pr);
-        re[j] = fmaR(m11, re[j], qr);
-        const R pi = m01 * im[j], qi = m10 * im[i];
-        im[i] = fmaR(m00, im[i], pi);
-        im[j] = fmaR(m11, im[j], qi);
+        const R pr = m01 * a[j].x, qr = m10 * a[i].x;
+        a[i].x = fmaR(m00, a[i].x, pr);
+        a[j].x = fmaR(m11, a[j].x, qr);
+        const R pi = m01 * a[j].y, qi = m10 * a[i].y;
+        a[i].y = fmaR(m00, a[i].y, pi);
+        a[j].y = fmaR(m11, a[j].y, qi);
     }
 }
 
 // [[a, i b], [i c, d]], a b c d real
 template <int A, typename R>
-__device__ __forceinline__ void op_ux(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
-    const R a = c[0], b = c[1], cc = c[2], d = c[3];
+__device__ __forceinline__ void op_ux(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
+    const R ca = c[0], b = c[1], cc = c[2], d = c[3];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         if (i & (1 << A)) continue;
         const int j = i | (1 << A);
-        const R p1 = b * im[j], p2 = b * re[j], q1 = cc * im[i], q2 = cc * re[i];
-        re[i] = fmaR(a, re[i], -p1);
-        im[i] = fmaR(a, im[i], p2);
-        re[j] = fmaR(d, re[j], -q1);
-        im[j] = fmaR(d, im[j], q2);
+        const R p1 = b * a[j].y, p2 = b * a[j].x, q1 = cc * a[i].y, q2 = cc * a[i].x;
+        a[i].x = fmaR(ca, a[i].x, -p1);
+        a[i].y = fmaR(ca, a[i].y, p2);
+        a[j].x = fmaR(d, a[j].x, -q1);
+        a[j].y = fmaR(d, a[j].y, q2);
     }
 }
 
 template <int A, typename R>
-__device__ __forceinline__ void op_p1(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_p1(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     const R pr = c[0], pi = c[1];
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-        if (i & (1 << A)) cmul_in_place(re[i], im[i], pr, pi);
+        if (i & (1 << A)) cmul_in_place(a[i].x, a[i].y, pr, pi);
 }
 
 template <int A, int B, typename R>
-__device__ __forceinline__ void op_p2(R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void op_p2(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     const R pr = c[0], pi = c[1];
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-        if ((i & (1 << A)) && (i & (1 << B))) cmul_in_place(re[i], im[i], pr, pi);
+        if ((i & (1 << A)) && (i & (1 << B))) cmul_in_place(a[i].x, a[i].y, pr, pi);
 }
 
 #define SW1(F)                                   \
     switch (op.a) {                              \
-    case 0: F<0>(re, im, c); break;              \
-    case 1: F<1>(re, im, c); break;              \
-    case 2: F<2>(re, im, c); break;              \
-    default: F<3>(re, im, c); break;             \
+    case 0: F<0>(a, c); break;              \
+    case 1: F<1>(a, c); break;              \
+    case 2: F<2>(a, c); break;              \
+    default: F<3>(a, c); break;             \
     }
 
 #define SW2(F)                                   \
     switch (op.a * 4 + op.b) {                   \
-    case 1: F<0, 1>(re, im, c); break;           \
-    case 2: F<0, 2>(re, im, c); break;           \
-    case 3: F<0, 3>(re, im, c); break;           \
-    case 4: F<1, 0>(re, im, c); break;           \
-    case 6: F<1, 2>(re, im, c); break;           \
-    case 7: F<1, 3>(re, im, c); break;           \
-    case 8: F<2, 0>(re, im, c); break;           \
-    case 9: F<2, 1>(re, im, c); break;           \
-    case 11: F<2, 3>(re, im, c); break;          \
-    case 12: F<3, 0>(re, im, c); break;          \
-    case 13: F<3, 1>(re, im, c); break;          \
-    case 14: F<3, 2>(re, im, c); break;          \
+    case 1: F<0, 1>(a, c); break;           \
+    case 2: F<0, 2>(a, c); break;           \
+    case 3: F<0, 3>(a, c); break;           \
+    case 4: F<1, 0>(a, c); break;           \
+    case 6: F<1, 2>(a, c); break;           \
+    case 7: F<1, 3>(a, c); break;           \
+    case 8: F<2, 0>(a, c); break;           \
+    case 9: F<2, 1>(a, c); break;           \
+    case 11: F<2, 3>(a, c); break;          \
+    case 12: F<3, 0>(a, c); break;          \
+    case 13: F<3, 1>(a, c); break;          \
+    case 14: F<3, 2>(a, c); break;          \
     default: break;                              \
     }
 
 // controls a < b, target c
 #define SW3(F)                                   \
     switch (op.a * 16 + op.b * 4 + op.c) {       \
-    case 0 * 16 + 1 * 4 + 2: F<0, 1, 2>(re, im, c); break; \
-    case 0 * 16 + 1 * 4 + 3: F<0, 1, 3>(re, im, c); break; \
-    case 0 * 16 + 2 * 4 + 1: F<0, 2, 1>(re, im, c); break; \
-    case 0 * 16 + 2 * 4 + 3: F<0, 2, 3>(re, im, c); break; \
-    case 0 * 16 + 3 * 4 + 1: F<0, 3, 1>(re, im, c); break; \
-    case 0 * 16 + 3 * 4 + 2: F<0, 3, 2>(re, im, c); break; \
-    case 1 * 16 + 2 * 4 + 0: F<1, 2, 0>(re, im, c); break; \
-    case 1 * 16 + 2 * 4 + 3: F<1, 2, 3>(re, im, c); break; \
-    case 1 * 16 + 3 * 4 + 0: F<1, 3, 0>(re, im, c); break; \
-    case 1 * 16 + 3 * 4 + 2: F<1, 3, 2>(re, im, c); break; \
-    case 2 * 16 + 3 * 4 + 0: F<2, 3, 0>(re, im, c); break; \
-    case 2 * 16 + 3 * 4 + 1: F<2, 3, 1>(re, im, c); break; \
+    case 0 * 16 + 1 * 4 + 2: F<0, 1, 2>(a, c); break; \
+    case 0 * 16 + 1 * 4 + 3: F<0, 1, 3>(a, c); break; \
+    case 0 * 16 + 2 * 4 + 1: F<0, 2, 1>(a, c); break; \
+    case 0 * 16 + 2 * 4 + 3: F<0, 2, 3>(a, c); break; \
+    case 0 * 16 + 3 * 4 + 1: F<0, 3, 1>(a, c); break; \
+    case 0 * 16 + 3 * 4 + 2: F<0, 3, 2>(a, c); break; \
+    case 1 * 16 + 2 * 4 + 0: F<1, 2, 0>(a, c); break; \
+    case 1 * 16 + 2 * 4 + 3: F<1, 2, 3>(a, c); break; \
+    case 1 * 16 + 3 * 4 + 0: F<1, 3, 0>(a, c); break; \
+    case 1 * 16 + 3 * 4 + 2: F<1, 3, 2>(a, c); break; \
+    case 2 * 16 + 3 * 4 + 0: F<2, 3, 0>(a, c); break; \
+    case 2 * 16 + 3 * 4 + 1: F<2, 3, 1>(a, c); break; \
     default: break;                              \
     }
 
 template <typename R>
-__device__ __forceinline__ void apply_op(const KOp op, R (&re)[NR], R (&im)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
     // the rotations and the CX of layered circuits first: a wave-uniform
     // if-chain reaches them in one or two branches
     const uint32_t ty = op.type;
@@ -278,7 +278,7 @@ __device__ __forceinline__ void apply_op(const KOp op, R (&re)[NR], R (&im)[NR],
         case KOP_X1: SW1(op_x1) break;
         case KOP_SWAP: SW2(op_swap) break;
         case KOP_CCX: SW3(op_ccx) break;
-        case KOP_DENSE: op_dense(re, im, c); break;
+        case KOP_DENSE: op_dense(a, c); break;
         case KOP_P1: SW1(op_p1) break;
         case KOP_P2: SW2(op_p2) break;
         default: break;
@@ -321,7 +321,7 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
 // ------------------------------------------------------------- pass body
 template <typename R>
 __device__ __forceinline__ void run_ops(const KStage *__restrict__ S, const KOp *__restrict__ ops,
-                                        const R *__restrict__ coefs, R (&re)[NR], R (&im)[NR]) {
+                                        const R *__restrict__ coefs, typename V2<R>::T (&a)[NR]) {
     // the next op's record is loaded before the current op runs (the op
     // array is followed by padding or coefficients inside the same plan
     // blob, so reading one record past a stage's last op stays in bounds)
@@ -329,7 +329,7 @@ __device__ __forceinline__ void run_ops(const KStage *__restrict__ S, const KOp 
     KOp op = ops[S->op_begin];
     for (uint32_t oi = S->op_begin; oi < oe; ++oi) {
         const KOp nx = ops[oi + 1];
-        apply_op<R>(op, re, im, coefs + op.coef);
+        apply_op<R>(op, a, coefs + op.coef);
         op = nx;
     }
 }
@@ -499,7 +499,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     // from global memory, the others from LDS; every stage but the last
     // scatters back to LDS.  (One call site keeps the amplitude registers
     // in place across the whole pass.)
-    R re[NR], im[NR];
+    C a[NR];
     for (uint32_t si = 0; si < ns; ++si) {
         const KStage *__restrict__ S = S0 + si;
         if (MF && S->kind == KSTAGE_MFMA) {
@@ -515,38 +515,38 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
             if (src_basis) {
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
-                    re[i] = g[i] == 0 ? R(1) : R(0);
-                    im[i] = R(0);
+                    a[i].x = g[i] == 0 ? R(1) : R(0);
+                    a[i].y = R(0);
                 }
             } else {
                 const C *src = static_cast<const C *>(src_);
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
                     const C y = src[g[i]];
-                    re[i] = y.x;
-                    im[i] = y.y;
+                    a[i].x = y.x;
+                    a[i].y = y.y;
                 }
                 if (scale) {
                     const R sc = R(scale[0]);
 #pragma unroll
-                    for (int i = 0; i < NR; ++i) { re[i] *= sc; im[i] *= sc; }
+                    for (int i = 0; i < NR; ++i) { a[i].x *= sc; a[i].y *= sc; }
                 }
             }
         } else {
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 const C y = lds[sl[i]];
-                re[i] = y.x;
-                im[i] = y.y;
+                a[i].x = y.x;
+                a[i].y = y.y;
             }
         }
-        run_ops<R>(S, ops, coefs, re, im);
+        run_ops<R>(S, ops, coefs, a);
         if (si + 1 == ns) break;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             C y;
-            y.x = re[i];
-            y.y = im[i];
+            y.x = a[i].x;
+            y.y = a[i].y;
             lds[sl[i]] = y;
         }
         lds_barrier();
@@ -562,16 +562,16 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             C y;
-            y.x = re[i];
-            y.y = im[i];
+            y.x = a[i].x;
+            y.y = a[i].y;
             dst[g[i]] = y;
         }
         if (ck) {
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 C y;
-                y.x = re[i];
-                y.y = im[i];
+                y.x = a[i].x;
+                y.y = a[i].y;
                 ck[g[i]] = y;
             }
         }
@@ -579,8 +579,8 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             C y;
-            y.x = re[i];
-            y.y = im[i];
+            y.x = a[i].x;
+            y.y = a[i].y;
             const uint64_t blk = g[i] >> block_bits;
             if ((store_mask[blk >> 6] >> (blk & 63)) & 1) {
                 dst[g[i]] = y;
@@ -591,7 +591,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     if (partials) {
         double acc = 0;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) acc += double(re[i]) * double(re[i]) + double(im[i]) * double(im[i]);
+        for (int i = 0; i < NR; ++i) acc += double(a[i].x) * double(a[i].x) + double(a[i].y) * double(a[i].y);
         __shared__ double red[16];
         const double sum = block_sum(acc, red);
         if (threadIdx.x == 0) partials[idx] = sum;
@@ -628,37 +628,37 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
         for (uint32_t k = 0; k < P->n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
         return base;
     };
-    R pr[NR], pi[NR];
+    C pa[NR];
     auto fetch = [&](uint32_t idx) {
         uint64_t g[NR];
         reg_goffs(S0, tile_base(idx) | gt0, g);
         if (src_basis) {
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
-                pr[i] = g[i] == 0 ? R(1) : R(0);
-                pi[i] = R(0);
+                pa[i].x = g[i] == 0 ? R(1) : R(0);
+                pa[i].y = R(0);
             }
         } else {
             const C *src = static_cast<const C *>(src_);
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 const C y = src[g[i]];
-                pr[i] = y.x;
-                pi[i] = y.y;
+                pa[i].x = y.x;
+                pa[i].y = y.y;
             }
         }
     };
     fetch(idx0);
     for (uint32_t idx = idx0; idx < n_idx; idx += stride) {
-        R re[NR], im[NR];
+        C a[NR];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) { re[i] = pr[i]; im[i] = pi[i]; }
+        for (int i = 0; i < NR; ++i) { a[i].x = pa[i].x; a[i].y = pa[i].y; }
         const uint32_t nxt = idx + stride;
         if (nxt < n_idx) fetch(nxt);
         if (scale) {
             const R sc = R(scale[0]);
 #pragma unroll
-            for (int i = 0; i < NR; ++i) { re[i] *= sc; im[i] *= sc; }
+            for (int i = 0; i < NR; ++i) { a[i].x *= sc; a[i].y *= sc; }
         }
         for (uint32_t si = 0; si < ns; ++si) {
             const KStage *__restrict__ S = S0 + si;
@@ -668,17 +668,17 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
                     const C y = lds[sl[i]];
-                    re[i] = y.x;
-                    im[i] = y.y;
+                    a[i].x = y.x;
+                    a[i].y = y.y;
                 }
             }
-            run_ops<R>(S, ops, coefs, re, im);
+            run_ops<R>(S, ops, coefs, a);
             if (si + 1 == ns) break;
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 C y;
-                y.x = re[i];
-                y.y = im[i];
+                y.x = a[i].x;
+                y.y = a[i].y;
                 lds[sl[i]] = y;
             }
             lds_barrier();
@@ -693,16 +693,16 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 C y;
-                y.x = re[i];
-                y.y = im[i];
+                y.x = a[i].x;
+                y.y = a[i].y;
                 dst[g[i]] = y;
             }
             if (ck) {
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
                     C y;
-                    y.x = re[i];
-                    y.y = im[i];
+                    y.x = a[i].x;
+                    y.y = a[i].y;
                     ck[g[i]] = y;
                 }
             }
@@ -710,8 +710,8 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 C y;
-                y.x = re[i];
-                y.y = im[i];
+                y.x = a[i].x;
+                y.y = a[i].y;
                 const uint64_t blk = g[i] >> block_bits;
                 if ((store_mask[blk >> 6] >> (blk & 63)) & 1) {
                     dst[g[i]] = y;
@@ -722,7 +722,7 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
         if (partials) {
             double acc = 0;
 #pragma unroll
-            for (int i = 0; i < NR; ++i) acc += double(re[i]) * double(re[i]) + double(im[i]) * double(im[i]);
+            for (int i = 0; i < NR; ++i) acc += double(a[i].x) * double(a[i].x) + double(a[i].y) * double(a[i].y);
             __shared__ double red[16];
             const double sum = block_sum(acc, red);
             if (threadIdx.x == 0) partials[idx] = sum;
