@@ -7,8 +7,15 @@ A step = one modifier batch: apply the edits, run the incremental update
 bytes must equal the incremental result.  ``value`` is the full simulation's
 achieved HBM throughput (algorithmic bytes / wall time of the full
 re-simulations).  The JSON line also carries the incremental p50/p99 latency
-and speedup, the complex64 tier, the pass kernel's roofline and the CPU
-oracle's rate on a bounded sample.
+and speedup, the complex64 tier, the pass kernel's roofline, and these
+legs (each can be switched off):
+  * append protocol: the same circuit built net by net with an update after
+    each, compared with full re-simulations at the same depth;
+  * large state: the layered family at 28 qubits (4 GiB, far above the
+    Infinity Cache) for an HBM-only figure;
+  * serving: 256 sessions of 12-28 qubits with Poisson modify+update
+    requests, both precisions;
+  * cpu baseline: the CPU oracle on a bounded sample, all threads and one.
 """
 import argparse
 import json
@@ -34,6 +41,12 @@ def pct(xs, p):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def fidelity(a, b):
+    """|<a|b>|^2 / (<a|a><b|b>) in FP64."""
+    import numpy as np
+    return float(abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
 
 
 def run_tier(Q, W, wl, dtype, steps, warmup):
@@ -177,6 +190,53 @@ def run_serving(Q, W, dtype, specs, keep_n=20):
         Q.qtask_server_destroy(sv)
 
 
+def run_append(Q, wl, dtype, tile_bits, low_bits, every=25):
+    """The paper's append protocol: build the circuit net by net and update
+    the state after each; every `every` nets also time a full
+    re-simulation at the same depth and compare the two bitwise."""
+    s = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, tile_bits=tile_bits, low_bits=low_bits)
+    inc, pairs, mismatches = [], [], 0
+    try:
+        for i, net in enumerate(wl.nets):
+            s.add_level(i)
+            for g in net:
+                s.add_gate(i, g)
+            st = s.update()
+            inc.append(st["wall_ms"])
+            if (i + 1) % every == 0:
+                h = s.hash()
+                sf = s.update(full=True)
+                mismatches += int(s.hash() != h)
+                pairs.append(sf["wall_ms"] / max(st["wall_ms"], 1e-9))
+    finally:
+        s.close()
+    return {"dtype": dtype, "nets": len(wl.nets), "update_ms_p50": pct(inc, 50), "update_ms_p99": pct(inc, 99),
+            "speedup_p50": pct(pairs, 50), "speedup_min": min(pairs), "speedup_at_full_depth": pairs[-1],
+            "mismatches": mismatches, "compared_depths": len(pairs)}
+
+
+def run_large(Q, W, n=28, levels=100, dtype="c128"):
+    """Full simulations of the layered family at a state far larger than the
+    256 MB Infinity Cache: HBM-only throughput of the pass kernel."""
+    wl = W.config(2, n=n, levels=levels, batches=1)
+    s = Q.Simulator(n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=1)
+    try:
+        s.build(wl.nets)
+        s.update()
+        best = None
+        for _ in range(3):
+            st = s.update(full=True)
+            if best is None or st["kernel_ms"] < best["kernel_ms"]:
+                best = st
+        o = Q.qtask_get_opts(s.h)
+    finally:
+        s.close()
+    gbs = best["bytes"] / (best["kernel_ms"] * 1e-3) / 1e9
+    return {"qubits": n, "levels": levels, "dtype": dtype, "state_gib": (1 << n) * (16 if dtype == "c128" else 8) / 2**30,
+            "full_ms": best["kernel_ms"], "passes": best["passes"], "gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+            "tile_bits": o.tile_bits, "low_bits": o.low_bits}
+
+
 def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
     """Time the CPU oracle (all host threads) on the first nets of the same
     circuit, adding nets until about min_s seconds of work."""
@@ -194,6 +254,16 @@ def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
         if time.perf_counter() - t0 >= min_s:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over the first nets (about 3 s)
+    psi1 = oracle.basis(wl.n)
+    g1 = 0
+    t1 = time.perf_counter()
+    for net in wl.nets[:max_nets]:
+        oracle.apply_gates(wl.n, psi1, list(net), 1)
+        g1 += len(net)
+        if time.perf_counter() - t1 >= min_s / 3:
+            break
+    dt1 = time.perf_counter() - t1
     return {
         "value": full_bytes_per_gate * gates / dt / 1e9,
         "unit": "GB/s",
@@ -203,6 +273,8 @@ def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
                   "GPU plan's bytes for the same gates / oracle time" % (used, gates, wl.n, dt, threads),
         "gate_amp_updates_per_s": gates * (1 << wl.n) / dt,
         "full_sim_s_extrapolated": dt * W.count_gates(wl.nets) / gates,
+        "value_1_thread": full_bytes_per_gate * g1 / dt1 / 1e9,
+        "gate_amp_updates_per_s_1_thread": g1 * (1 << wl.n) / dt1,
     }
 
 
@@ -214,11 +286,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-append", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU: the state and the serving sessions are not sharded across GPUs "
+              "(the design notes describe how they would be)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2210_01076_amd import qtask as Q
@@ -232,11 +306,10 @@ def main():
     if not args.no_c64:
         sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup)
         import numpy as np
-        from oracle import oracle
         a = sim128.state()
-        b = sim64.state()
-        r64["max_abs_vs_c128"] = float(np.max(np.abs(a - b.astype(np.complex128))))
-        r64["fidelity_vs_c128"] = oracle.fidelity(a, b)
+        b = sim64.state().astype(np.complex128)
+        r64["max_abs_vs_c128"] = float(np.max(np.abs(a - b)))
+        r64["fidelity_vs_c128"] = fidelity(a, b)
         sim64.close()
     sim128.close()
 
@@ -255,6 +328,17 @@ def main():
         log("serving c128 p50 %.1f ms p99 %.1f ms %.1f upd/s | c64 p50 %.1f ms p99 %.1f ms %.1f upd/s" % (
             s128["latency_ms_p50"], s128["latency_ms_p99"], s128["updates_per_s"],
             s64["latency_ms_p50"], s64["latency_ms_p99"], s64["updates_per_s"]))
+
+    append = None
+    if not args.no_append:
+        append = run_append(Q, wl, "c128", r128["tile_bits"], r128["low_bits"])
+        log("append protocol: update p50 %.2f ms, speedup vs full p50 %.1f (at full depth %.1f)" % (
+            append["update_ms_p50"], append["speedup_p50"], append["speedup_at_full_depth"]))
+    large = None
+    if not args.no_large:
+        large = run_large(Q, W)
+        log("28-qubit complex128 full simulation: %.1f ms, %.0f GB/s (%.2f of peak)" % (
+            large["full_ms"], large["gbs"], large["frac_of_peak"]))
 
     per_gate = r128["pass_bytes"] * r128["passes_per_full"] / W.count_gates(nets)
     cpu = None if args.no_cpu else cpu_baseline(W, wl, per_gate)
@@ -305,6 +389,8 @@ def main():
                      "avg_launch_ms": r128["launch_ms"], "launches_timed": r128["launches"],
                      "block": 1 << (r128["tile_bits"] - 4),
                      "scope": "every pass launch of the timed steps (incremental and full), complex128"},
+        "append_protocol": append,
+        "large_state": large,
         "serving": serving,
         "cpu_baseline": cpu,
     }
