@@ -190,11 +190,13 @@ def run_serving(Q, W, dtype, specs, keep_n=20):
         Q.qtask_server_destroy(sv)
 
 
-def run_append(Q, wl, dtype, tile_bits, low_bits, every=25):
+def run_append(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10):
     """The paper's append protocol: build the circuit net by net and update
     the state after each; every `every` nets also time a full
-    re-simulation at the same depth and compare the two bitwise."""
-    s = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, tile_bits=tile_bits, low_bits=low_bits)
+    re-simulation at the same depth and compare the two bitwise.  The
+    session keeps a checkpoint every `ckpt_nets` nets (2.5 GiB at 24 qubits
+    for the 400 nets), so an update replays at most that many nets."""
+    s = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=ckpt_nets, tile_bits=tile_bits, low_bits=low_bits)
     inc, pairs, mismatches = [], [], 0
     try:
         for i, net in enumerate(wl.nets):
@@ -210,7 +212,8 @@ def run_append(Q, wl, dtype, tile_bits, low_bits, every=25):
                 pairs.append(sf["wall_ms"] / max(st["wall_ms"], 1e-9))
     finally:
         s.close()
-    return {"dtype": dtype, "nets": len(wl.nets), "update_ms_p50": pct(inc, 50), "update_ms_p99": pct(inc, 99),
+    return {"dtype": dtype, "nets": len(wl.nets), "ckpt_nets": ckpt_nets,
+            "update_ms_p50": pct(inc, 50), "update_ms_p99": pct(inc, 99),
             "speedup_p50": pct(pairs, 50), "speedup_min": min(pairs), "speedup_at_full_depth": pairs[-1],
             "mismatches": mismatches, "compared_depths": len(pairs)}
 
