@@ -73,12 +73,20 @@ struct KStage {
 // its last stage stores straight from registers (both through their own
 // global maps, chosen so that consecutive lanes touch consecutive
 // addresses); the stages in between exchange data through LDS.
+// The global offset of a tile is its index with bits deposited at the
+// non-tile qubits.  Those qubits form at most b + 1 runs of consecutive
+// positions; run r moves tile-index bits [src, src + len) to global bits
+// [dst, dst + len), packed as src | len << 8 | dst << 16.
+#define QK_MAX_RUNS (QK_MAX_TILE_BITS + 1)
+
 struct KPass {
     uint8_t nonq_pos[QK_MAX_QUBITS];    // global bit of tile-index bit k
     uint8_t pad[2];
     uint32_t n_nonq;                    // n - b
     uint32_t n_thr;                     // b - QK_G
     uint32_t stage_begin, stage_count;  // stage_count >= 1
+    uint32_t n_runs;                    // runs of consecutive non-tile qubits
+    uint32_t run[QK_MAX_RUNS];          // deposit runs (see above)
 };
 
 // Launch arguments of one pass (passed by value).

@@ -477,6 +477,35 @@ __device__ __forceinline__ void mfma_stage(const KStage *__restrict__ S, const R
 // One tile (number idx of the pass, or tile_list[idx]).  The first stage's
 // registers come straight from global memory, the middle stages go through
 // LDS, the last stage's registers go straight back to global memory.
+// Deposit runs of a pass, read once into scalar registers (a fixed-size
+// unrolled copy keeps them out of memory inside the tile loop).
+struct TileRuns {
+    uint32_t n;
+    uint32_t run[QK_MAX_RUNS];
+};
+
+__device__ __forceinline__ TileRuns load_runs(const KPass *__restrict__ P) {
+    TileRuns tr;
+    tr.n = P->n_runs;
+#pragma unroll
+    for (int r = 0; r < QK_MAX_RUNS; ++r) tr.run[r] = P->run[r];
+    return tr;
+}
+
+// Global offset of tile `tile`: its index bits deposited at the non-tile
+// qubits, one run of consecutive qubits at a time.
+__device__ __forceinline__ uint64_t tile_origin(const TileRuns &tr, uint32_t tile) {
+    uint64_t base = 0;
+#pragma unroll
+    for (int r = 0; r < QK_MAX_RUNS; ++r) {
+        if (r < int(tr.n)) {
+            const uint32_t src = tr.run[r] & 0xffu, len = (tr.run[r] >> 8) & 0xffu, dst = tr.run[r] >> 16;
+            base |= uint64_t((tile >> src) & ((1u << len) - 1u)) << dst;
+        }
+    }
+    return base;
+}
+
 template <typename R, bool MF>
 __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restrict__ tile_list, void *dst_,
                                           const void *src_, void *ckpt_, const KPass *__restrict__ P,
@@ -492,8 +521,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     const KStage *__restrict__ S0 = stages + P->stage_begin;
     const KStage *__restrict__ SL = S0 + (ns - 1);
     const uint32_t tile = tile_list ? tile_list[idx] : idx;
-    uint64_t base = 0;
-    for (uint32_t k = 0; k < P->n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
+    const uint64_t base = tile_origin(load_runs(P), tile);
 
     // One loop over the stages with a single op-loop site: stage 0 gathers
     // from global memory, the others from LDS; every stage but the last
@@ -622,11 +650,9 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
     const KStage *__restrict__ SL = S0 + (ns - 1);
     const uint64_t gt0 = thr_glb<R>(S0, n_thr, t);
     const uint64_t gtl = thr_glb<R>(SL, n_thr, t);
+    const TileRuns tr = load_runs(P);
     auto tile_base = [&](uint32_t idx) {
-        const uint32_t tile = tile_list ? tile_list[idx] : idx;
-        uint64_t base = 0;
-        for (uint32_t k = 0; k < P->n_nonq; ++k) base |= uint64_t((tile >> k) & 1u) << P->nonq_pos[k];
-        return base;
+        return tile_origin(tr, tile_list ? tile_list[idx] : idx);
     };
     C pa[NR];
     auto fetch = [&](uint32_t idx) {
@@ -972,11 +998,14 @@ __global__ void qk_copy_blocks(void *dst_, const void *src_, const uint32_t *blo
     }
 }
 
-// Plain streaming copy: each thread moves 32-byte words with a grid stride.
-__global__ void __launch_bounds__(256) qk_copy(double4 *__restrict__ dst, const double4 *__restrict__ src,
-                                               uint64_t n) {
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-        dst[i] = src[i];
+// Plain streaming copy: each thread moves one 16-byte word with non-temporal
+// accesses, one short-lived workgroup per 4 KiB (the form that reaches the
+// highest copy rate on the device; a grid-stride loop over fewer workgroups
+// and unrolled variants measured 15-25 % lower).
+typedef double qk_nd2 __attribute__((ext_vector_type(2)));
+__global__ void __launch_bounds__(256) qk_copy(qk_nd2 *__restrict__ dst, const qk_nd2 *__restrict__ src, uint64_t n) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1164,10 +1193,11 @@ hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s) 
 
 hipError_t launch_copy(void *dst, const void *src, uint64_t n32, hipStream_t s) {
     (void)hipGetLastError();
-    uint64_t g = (n32 + 255) / 256;
-    if (g > 256 * 64) g = 256 * 64;
-    hipLaunchKernelGGL(qk_copy, dim3(uint32_t(g < 1 ? 1 : g)), dim3(256), 0, s, static_cast<double4 *>(dst),
-                       static_cast<const double4 *>(src), n32);
+    const uint64_t n16 = 2 * n32;
+    const uint64_t g = (n16 + 255) / 256;
+    if (g > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(qk_copy, dim3(uint32_t(g < 1 ? 1 : g)), dim3(256), 0, s, static_cast<qk_nd2 *>(dst),
+                       static_cast<const qk_nd2 *>(src), n16);
     return hipGetLastError();
 }
 

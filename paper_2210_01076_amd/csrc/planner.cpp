@@ -341,8 +341,15 @@ void pack_blob(SegmentPlan &sp) {
         std::memset(&P, 0, sizeof(P));
         auto goff = [&](int p) { return uint64_t(1) << ps.qlist[p]; };
         int k = 0;
-        for (int q = 0; q < pp.n; ++q)
-            if (!((ps.qmask >> q) & 1)) P.nonq_pos[k++] = uint8_t(q);
+        for (int q = 0; q < pp.n; ++q) {
+            if ((ps.qmask >> q) & 1) continue;
+            if (q == 0 || ((ps.qmask >> (q - 1)) & 1)) {
+                if (P.n_runs >= QK_MAX_RUNS) throw std::logic_error("too many non-tile runs");
+                P.run[P.n_runs++] = uint32_t(k) | uint32_t(q) << 16;
+            }
+            P.run[P.n_runs - 1] += 1u << 8;
+            P.nonq_pos[k++] = uint8_t(q);
+        }
         P.n_nonq = uint32_t(k);
         P.n_thr = uint32_t(n_thr);
         P.stage_begin = uint32_t(si);
@@ -488,6 +495,17 @@ std::string validate_plan(const SegmentPlan &sp) {
         for (int q = 0; q < std::max(0, std::min(pp.c, pp.b - 3)); ++q)
             if (ps.qlist[q] != q) { err << "pass " << pi << ": low bits"; return err.str(); }
         if (P.stage_count < 1) { err << "pass " << pi << ": no stage"; return err.str(); }
+        {
+            // the deposit runs must send tile-index bit k to nonq_pos[k], in order
+            uint32_t k = 0;
+            for (uint32_t r = 0; r < P.n_runs; ++r) {
+                const uint32_t src = P.run[r] & 0xff, len = (P.run[r] >> 8) & 0xff, dst = P.run[r] >> 16;
+                if (src != k || len == 0) { err << "pass " << pi << ": deposit runs"; return err.str(); }
+                for (uint32_t j = 0; j < len; ++j, ++k)
+                    if (k >= P.n_nonq || P.nonq_pos[k] != dst + j) { err << "pass " << pi << ": deposit runs"; return err.str(); }
+            }
+            if (k != P.n_nonq || P.n_nonq != uint32_t(pp.n - b)) { err << "pass " << pi << ": deposit runs"; return err.str(); }
+        }
         for (uint32_t which : {P.stage_begin, P.stage_begin + P.stage_count - 1}) {
             const KStage &S = ks[which];
             if (S.kind != KSTAGE_LIST) { err << "pass " << pi << ": first/last stage must be a list stage"; return err.str(); }
