@@ -334,11 +334,15 @@ __device__ __forceinline__ void run_ops(const KStage *__restrict__ S, const KOp 
     }
 }
 
+// The loops run over the table's full length with branch-free selects: the
+// table is read by a few wide scalar loads, with one wait, and no lane
+// diverges.  Entries past the stage's thread bits are zero and so are the
+// corresponding bits of t (t < 2^n_thr), so they add nothing.
 template <typename R>
-__device__ __forceinline__ uint32_t thr_lds(const KStage *__restrict__ S, uint32_t n_thr, uint32_t t) {
+__device__ __forceinline__ uint32_t thr_lds(const KStage *__restrict__ S, uint32_t, uint32_t t) {
     uint32_t o = 0;
-    for (uint32_t k = 0; k < n_thr; ++k)
-        if ((t >> k) & 1u) o ^= S->thr_off[k];
+#pragma unroll
+    for (int k = 0; k < QK_MAX_THR_BITS; ++k) o ^= S->thr_off[k] & (0u - ((t >> k) & 1u));
     return o;
 }
 
@@ -367,10 +371,10 @@ __device__ __forceinline__ void reg_goffs(const KStage *__restrict__ S, uint64_t
 }
 
 template <typename R>
-__device__ __forceinline__ uint64_t thr_glb(const KStage *__restrict__ S, uint32_t n_thr, uint32_t t) {
+__device__ __forceinline__ uint64_t thr_glb(const KStage *__restrict__ S, uint32_t, uint32_t t) {
     uint64_t o = 0;
-    for (uint32_t k = 0; k < n_thr; ++k)
-        if ((t >> k) & 1u) o |= S->g_thr[k];
+#pragma unroll
+    for (int k = 0; k < QK_MAX_THR_BITS; ++k) o |= S->g_thr[k] & (uint64_t(0) - ((t >> k) & 1u));
     return o;
 }
 
