@@ -55,13 +55,16 @@ struct KOp {
     uint32_t coef;          // offset into the coefficient array (in R units)
 };
 
+// The first 64 bytes of a stage (register and thread maps, op range, kind)
+// are what every stage of every tile needs; the kernel reads them with one
+// scalar load.
 struct KStage {
     uint32_t reg_bit[QK_G];           // LDS slot contribution of register-index bit j
     uint32_t thr_off[QK_MAX_THR_BITS];// LDS slot contribution of thread-index bit k
+    uint32_t op_begin, op_count;      // ops of the stage; consecutive stages have consecutive ranges
+    uint32_t kind;                    // KStageKind
     uint64_t g_bit[QK_G];             // first/last stage: global offset of register-index bit j
     uint64_t g_thr[QK_MAX_THR_BITS];  // first/last stage: global offset of thread-index bit k
-    uint32_t op_begin, op_count;
-    uint32_t kind;                    // KStageKind
     uint32_t k;                       // MFMA stage: qubits of the dense unitary
     uint32_t coef;                    // MFMA stage: offset of the 2^k x 2^k matrix (interleaved)
     uint32_t n_col_bits;              // MFMA stage: b - k

@@ -319,15 +319,33 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
 }
 
 // ------------------------------------------------------------- pass body
+// The leading fields of a stage record, read with one wide scalar load.
+struct StageHead {
+    uint32_t reg_bit[QK_G];
+    uint32_t thr_off[QK_MAX_THR_BITS];
+    uint32_t op_begin, op_count;
+    uint32_t kind;
+};
+static_assert(sizeof(StageHead) == 64, "stage head is one 64-byte scalar load");
+static_assert(offsetof(KStage, thr_off) == offsetof(StageHead, thr_off) &&
+                  offsetof(KStage, op_begin) == offsetof(StageHead, op_begin) &&
+                  offsetof(KStage, kind) == offsetof(StageHead, kind),
+              "stage head mirrors the start of KStage");
+
+__device__ __forceinline__ StageHead stage_head(const KStage *__restrict__ S) {
+    return *reinterpret_cast<const StageHead *>(S);
+}
+
+// Runs the stage's ops.  `op` holds the stage's first record on entry and the
+// record after its last one on exit: consecutive stages have consecutive op
+// ranges, so it is the next stage's first record.  Each record is loaded
+// before the previous op runs (the op array is followed by a spare record
+// inside the plan blob, so the read past the last op stays in bounds).
 template <typename R>
-__device__ __forceinline__ void run_ops(const KStage *__restrict__ S, const KOp *__restrict__ ops,
-                                        const R *__restrict__ coefs, typename V2<R>::T (&a)[NR]) {
-    // the next op's record is loaded before the current op runs (the op
-    // array is followed by padding or coefficients inside the same plan
-    // blob, so reading one record past a stage's last op stays in bounds)
-    const uint32_t oe = S->op_begin + S->op_count;
-    KOp op = ops[S->op_begin];
-    for (uint32_t oi = S->op_begin; oi < oe; ++oi) {
+__device__ __forceinline__ void run_ops(const StageHead &h, const KOp *__restrict__ ops, const R *__restrict__ coefs,
+                                        typename V2<R>::T (&a)[NR], KOp &op) {
+    const uint32_t oe = h.op_begin + h.op_count;
+    for (uint32_t oi = h.op_begin; oi < oe; ++oi) {
         const KOp nx = ops[oi + 1];
         apply_op<R>(op, a, coefs + op.coef);
         op = nx;
@@ -338,18 +356,17 @@ __device__ __forceinline__ void run_ops(const KStage *__restrict__ S, const KOp 
 // table is read by a few wide scalar loads, with one wait, and no lane
 // diverges.  Entries past the stage's thread bits are zero and so are the
 // corresponding bits of t (t < 2^n_thr), so they add nothing.
-template <typename R>
-__device__ __forceinline__ uint32_t thr_lds(const KStage *__restrict__ S, uint32_t, uint32_t t) {
+__device__ __forceinline__ uint32_t thr_lds(const StageHead &h, uint32_t t) {
     uint32_t o = 0;
 #pragma unroll
-    for (int k = 0; k < QK_MAX_THR_BITS; ++k) o ^= S->thr_off[k] & (0u - ((t >> k) & 1u));
+    for (int k = 0; k < QK_MAX_THR_BITS; ++k) o ^= h.thr_off[k] & (0u - ((t >> k) & 1u));
     return o;
 }
 
 // Per-register LDS slots (XOR) and global offsets (OR) from the per-bit
 // contributions; each register adds one bit to an earlier one.
-__device__ __forceinline__ void reg_slots(const KStage *__restrict__ S, uint32_t bt, uint32_t (&sl)[NR]) {
-    const uint32_t b0 = S->reg_bit[0], b1 = S->reg_bit[1], b2 = S->reg_bit[2], b3 = S->reg_bit[3];
+__device__ __forceinline__ void reg_slots(const StageHead &h, uint32_t bt, uint32_t (&sl)[NR]) {
+    const uint32_t b0 = h.reg_bit[0], b1 = h.reg_bit[1], b2 = h.reg_bit[2], b3 = h.reg_bit[3];
     sl[0] = bt;
 #pragma unroll
     for (int i = 1; i < NR; ++i) {
@@ -370,8 +387,7 @@ __device__ __forceinline__ void reg_goffs(const KStage *__restrict__ S, uint64_t
     }
 }
 
-template <typename R>
-__device__ __forceinline__ uint64_t thr_glb(const KStage *__restrict__ S, uint32_t, uint32_t t) {
+__device__ __forceinline__ uint64_t thr_glb(const KStage *__restrict__ S, uint32_t t) {
     uint64_t o = 0;
 #pragma unroll
     for (int k = 0; k < QK_MAX_THR_BITS; ++k) o |= S->g_thr[k] & (uint64_t(0) - ((t >> k) & 1u));
@@ -532,18 +548,20 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     // scatters back to LDS.  (One call site keeps the amplitude registers
     // in place across the whole pass.)
     C a[NR];
+    KOp op = ops[S0->op_begin];
     for (uint32_t si = 0; si < ns; ++si) {
         const KStage *__restrict__ S = S0 + si;
-        if (MF && S->kind == KSTAGE_MFMA) {
+        const StageHead h = stage_head(S);
+        if (MF && h.kind == KSTAGE_MFMA) {
             mfma_stage<R>(S, coefs, lds);
             lds_barrier();
             continue;
         }
         uint32_t sl[NR];
-        reg_slots(S, thr_lds<R>(S, n_thr, t), sl);
+        reg_slots(h, thr_lds(h, t), sl);
         if (si == 0) {
             uint64_t g[NR];
-            reg_goffs(S, base | thr_glb<R>(S, n_thr, t), g);
+            reg_goffs(S, base | thr_glb(S, t), g);
             if (src_basis) {
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
@@ -572,7 +590,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
                 a[i].y = y.y;
             }
         }
-        run_ops<R>(S, ops, coefs, a);
+        run_ops<R>(h, ops, coefs, a, op);
         if (si + 1 == ns) break;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -589,7 +607,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     C *dst = static_cast<C *>(dst_);
     C *ck = static_cast<C *>(ckpt_);
     uint64_t g[NR];
-    reg_goffs(SL, base | thr_glb<R>(SL, n_thr, t), g);
+    reg_goffs(SL, base | thr_glb(SL, t), g);
     if (!store_mask) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -652,8 +670,8 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
     const uint32_t ns = P->stage_count;
     const KStage *__restrict__ S0 = stages + P->stage_begin;
     const KStage *__restrict__ SL = S0 + (ns - 1);
-    const uint64_t gt0 = thr_glb<R>(S0, n_thr, t);
-    const uint64_t gtl = thr_glb<R>(SL, n_thr, t);
+    const uint64_t gt0 = thr_glb(S0, t);
+    const uint64_t gtl = thr_glb(SL, t);
     const TileRuns tr = load_runs(P);
     auto tile_base = [&](uint32_t idx) {
         return tile_origin(tr, tile_list ? tile_list[idx] : idx);
@@ -679,6 +697,7 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
         }
     };
     fetch(idx0);
+    const KOp op0 = ops[S0->op_begin];
     for (uint32_t idx = idx0; idx < n_idx; idx += stride) {
         C a[NR];
 #pragma unroll
@@ -690,10 +709,11 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
 #pragma unroll
             for (int i = 0; i < NR; ++i) { a[i].x *= sc; a[i].y *= sc; }
         }
+        KOp op = op0;
         for (uint32_t si = 0; si < ns; ++si) {
-            const KStage *__restrict__ S = S0 + si;
+            const StageHead h = stage_head(S0 + si);
             uint32_t sl[NR];
-            reg_slots(S, thr_lds<R>(S, n_thr, t), sl);
+            reg_slots(h, thr_lds(h, t), sl);
             if (si > 0) {
 #pragma unroll
                 for (int i = 0; i < NR; ++i) {
@@ -702,7 +722,7 @@ __device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, ui
                     a[i].y = y.y;
                 }
             }
-            run_ops<R>(S, ops, coefs, a);
+            run_ops<R>(h, ops, coefs, a, op);
             if (si + 1 == ns) break;
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
