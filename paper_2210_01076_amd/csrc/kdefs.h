@@ -42,7 +42,8 @@ enum KOpType : uint8_t {
     KOP_UR = 12,   // real 2x2 on bit a (H, RY)                 coef: m00 m01 m10 m11 (4 reals)
     KOP_UX = 13,   // [[a, ib], [ic, d]] with a,b,c,d real (RX)  coef: a b c d (4)
     KOP_P1 = 14,   // diag(1, p) on bit a (Z, S, T, ...)         coef: p (2)
-    KOP_P2 = 15    // diag(1, 1, 1, p) on (a, b) (CZ, CP)        coef: p (2)
+    KOP_P2 = 15,   // diag(1, 1, 1, p) on (a, b) (CZ, CP)        coef: p (2)
+    KOP_GPH = 16   // every amplitude times g (no qubits)       coef: g (2)
 };
 
 enum KStageKind : uint32_t {

@@ -219,6 +219,13 @@ __device__ __forceinline__ void op_p2(typename V2<R>::T (&a)[NR], const R *__res
         if ((i & (1 << A)) && (i & (1 << B))) cmul_in_place(a[i].x, a[i].y, pr, pi);
 }
 
+template <typename R>
+__device__ __forceinline__ void op_gph(typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
+    const R gr = c[0], gi = c[1];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) cmul_in_place(a[i].x, a[i].y, gr, gi);
+}
+
 #define SW1(F)                                   \
     switch (op.a) {                              \
     case 0: F<0>(a, c); break;              \
@@ -281,6 +288,7 @@ __device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR
         case KOP_DENSE: op_dense(a, c); break;
         case KOP_P1: SW1(op_p1) break;
         case KOP_P2: SW2(op_p2) break;
+        case KOP_GPH: op_gph<R>(a, c); break;
         default: break;
         }
     }

@@ -91,6 +91,7 @@ double LGate::flops_per_amp() const {
     case KOP_D1: case KOP_A1: return 6;
     case KOP_P1: return 3;        // half of the amplitudes get a phase
     case KOP_P2: return 1.5;      // a quarter of the amplitudes get a phase
+    case KOP_GPH: return 6;       // every amplitude times a complex scalar
     case KOP_DENSE: return 8.0 * (1 << nq) - 2;
     default: return 0;            // exact exchanges
     }

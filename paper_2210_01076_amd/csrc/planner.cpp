@@ -110,6 +110,47 @@ LGate merge_1q(const LGate &later, const LGate &earlier) {
 }
 
 // cost units (register FMAs per amplitude) used to decide merges
+// A diagonal one-qubit op diag(d0, d1) runs as diag(1, d1/d0), which
+// multiplies half the amplitudes instead of all of them; the factors d0 of a
+// segment are collected, in plan order, into one scalar that the segment's
+// last stage applies to every amplitude.  A scalar factor commutes with every
+// gate, so the segment's result is unchanged up to rounding.  Plans whose
+// last stage is a fused dense unitary keep their diagonal ops as they are.
+void factor_phases(std::vector<PPass> &passes) {
+    if (passes.empty() || passes.back().stages.empty()) return;
+    PStage &last = passes.back().stages.back();
+    if (!last.U.empty() || last.mfma) return;
+    cd g(1, 0);
+    bool any = false;
+    for (auto &ps : passes)
+        for (auto &st : ps.stages) {
+            if (!st.U.empty() || st.mfma) continue;
+            bool changed = false;
+            for (auto &op : st.ops) {
+                if (op.kop != KOP_D1) continue;
+                const cd d0 = op.m[0];
+                g *= d0;
+                op.m = {cd(1, 0), cd(0, 0), cd(0, 0), op.m[3] / d0};
+                op.kop = KOP_P1;
+                set_1q_coef(op);
+                changed = any = true;
+            }
+            if (changed) {
+                st.flops = 0;
+                for (const auto &op : st.ops) st.flops += op.flops_per_amp();
+            }
+        }
+    if (!any) return;
+    LGate gp;
+    gp.kop = KOP_GPH;
+    gp.nq = 0;
+    gp.m = {g};
+    gp.diagonal = gp.monomial = true;
+    gp.coef = {g.real(), g.imag()};
+    last.flops += gp.flops_per_amp();
+    last.ops.push_back(gp);
+}
+
 double op_cost(const LGate &g) {
     switch (g.kop) {
     case KOP_U1: return 8;
@@ -403,7 +444,7 @@ void pack_blob(SegmentPlan &sp) {
                 for (const LGate &g : st.ops) {
                     KOp &o = ko[oi++];
                     o.type = g.kop;
-                    o.a = uint8_t(reg_of(g.q[0]));
+                    o.a = g.nq > 0 ? uint8_t(reg_of(g.q[0])) : 0;
                     o.b = g.nq > 1 ? uint8_t(reg_of(g.q[1])) : 0;
                     o.c = g.nq > 2 ? uint8_t(reg_of(g.q[2])) : 0;
                     if (g.kop == KOP_CCX && o.a > o.b) std::swap(o.a, o.b);
@@ -459,6 +500,7 @@ SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp, ui
     sp.pp = pp;
     Packer pk(pp);
     sp.passes = pk.pack_passes(ops);
+    factor_phases(sp.passes);
     if (sp.passes.empty()) {
         // a segment without gates still carries the state across its
         // boundary (restore, checkpoint write, norm): one pass, one empty stage
