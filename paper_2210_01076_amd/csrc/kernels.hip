@@ -428,6 +428,17 @@ template <> struct MfmaT<float> {
     static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
+// Element of the real block matrix [[Ur, -Ui], [Ui, Ur]] at real row rr and
+// real column kk.  Whether it is a real or an imaginary part, and its sign,
+// depend only on the halves rr and kk fall in.
+template <typename R, int DIM>
+__device__ __forceinline__ R block_elem(const R *__restrict__ U, int rr, int kk) {
+    const int ur = rr & (DIM - 1), uk = kk & (DIM - 1);
+    const bool top = rr < DIM, right = kk >= DIM;
+    const R v = U[2 * (ur * DIM + uk) + (top == right ? 1 : 0)];
+    return (top && right) ? -v : v;
+}
+
 template <typename R, int K>
 __device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const R *__restrict__ coefs,
                                              R *__restrict__ lr) {
@@ -437,53 +448,75 @@ __device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const
     constexpr int RB = MR / 16;     // row blocks
     constexpr int KS = MR / 4;      // inner steps of 4
     constexpr int CB = 64 / DIM;    // column blocks per wave
+    // the whole A operand stays in registers while it fits: 4 * KS * RB
+    // bytes per lane (64 VGPRs at K = 5 in FP32, 32 at K = 4 in FP64)
+    constexpr bool A_REG = sizeof(R) == 4 ? K <= 5 : K <= 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const R *__restrict__ U = coefs + S->coef;
-    const uint32_t ncb = S->n_col_bits;
-    // LDS slot contribution of this lane's and each column block's column bits
+    // LDS slot contributions (the slot map is linear over the bits of the
+    // row and column indices): unrolled branch-free selects over the tables,
+    // whose unused entries are zero
     uint32_t lane_off = 0;
-    for (int j = 0; j < 4; ++j)
-        if ((lane >> j) & 1) lane_off ^= S->col_off[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lane_off ^= S->col_off[j] & (0u - ((uint32_t(lane) >> j) & 1u));
     uint32_t cb_off[CB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         const uint32_t blk = uint32_t(wave * CB + cb);
+        uint32_t o = lane_off;
+#pragma unroll
+        for (int j = 4; j < QK_MAX_TILE_BITS; ++j) o ^= S->col_off[j] & (0u - ((blk >> (j - 4)) & 1u));
+        cb_off[cb] = o;
+    }
+    uint32_t rbit[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) rbit[j] = S->row_off[1 << j];
+    auto row_slot = [&](int r) {
         uint32_t o = 0;
-        for (uint32_t j = 4; j < ncb; ++j)
-            if ((blk >> (j - 4)) & 1) o ^= S->col_off[j];
-        cb_off[cb] = o ^ lane_off;
+#pragma unroll
+        for (int j = 0; j < K; ++j) o ^= rbit[j] & (0u - ((uint32_t(r) >> j) & 1u));
+        return o;
+    };
+    R areg[A_REG ? KS : 1][A_REG ? RB : 1];
+    if constexpr (A_REG) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) areg[s][rb] = block_elem<R, DIM>(U, 16 * rb + (lane & 15), 4 * s + (lane >> 4));
     }
     typename M::acc_t acc[RB][CB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = typename M::acc_t{0, 0, 0, 0};
-#pragma unroll 2
-    for (int s = 0; s < KS; ++s) {
+    auto step = [&](int s, auto a_of) {
         const int kk = 4 * s + (lane >> 4);          // real inner index of this lane
-        const int uk = kk & (DIM - 1);
+        const uint32_t roff = row_slot(kk & (DIM - 1));
         const int part = kk >= DIM ? 1 : 0;          // 0: Xr, 1: Xi
-        const uint32_t roff = S->row_off[uk];
         R bv[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) bv[cb] = lr[2 * (cb_off[cb] ^ roff) + part];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            const int rr = 16 * rb + (lane & 15);    // real output row of this lane's A value
-            const int ur = rr & (DIM - 1);
-            const R re = U[2 * (ur * DIM + uk)], im = U[2 * (ur * DIM + uk) + 1];
-            const bool top = rr < DIM;
-            const R av = (top == (part == 0)) ? re : (top ? -im : im);
+            const R av = a_of(s, rb, kk);
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = M::mma(av, bv[cb], acc[rb][cb]);
         }
+    };
+    if constexpr (A_REG) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) step(s, [&](int s_, int rb, int) { return areg[s_][rb]; });
+    } else {
+#pragma unroll 2
+        for (int s = 0; s < KS; ++s)
+            step(s, [&](int, int rb, int kk) { return block_elem<R, DIM>(U, 16 * rb + (lane & 15), kk); });
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rr = 16 * rb + M::row(lane, i);
-            const uint32_t roff = S->row_off[rr & (DIM - 1)];
+            const uint32_t roff = row_slot(rr & (DIM - 1));
             const int part = rr >= DIM ? 1 : 0;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) lr[2 * (cb_off[cb] ^ roff) + part] = acc[rb][cb][i];
