@@ -507,7 +507,7 @@ __device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const
 #pragma unroll
         for (int s = 0; s < KS; ++s) step(s, [&](int s_, int rb, int) { return areg[s_][rb]; });
     } else {
-#pragma unroll 2
+#pragma unroll 4
         for (int s = 0; s < KS; ++s)
             step(s, [&](int, int rb, int kk) { return block_elem<R, DIM>(U, 16 * rb + (lane & 15), kk); });
     }
