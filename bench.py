@@ -240,6 +240,60 @@ def run_large(Q, W, n=28, levels=100, dtype="c128"):
             "tile_bits": o.tile_bits, "low_bits": o.low_bits}
 
 
+MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # dense FP32 / FP64 matrix-core peaks
+
+
+def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 << 20):
+    """Configuration 3: the layered family at 30 qubits with every stage fused
+    into a dense k-qubit unitary on the matrix cores, complex64 (renormalised
+    at every 50-level segment end) against complex128, both fused; then the
+    same circuit on the gate-list path (complex64, autotuned) for
+    comparison."""
+    import numpy as np
+
+    wl = W.config(3, n=n, levels=levels)
+    common = dict(device=0, ckpt_interval=50, max_ckpts=1)
+    out = {"qubits": n, "levels": levels, "fuse_width": k, "tile_bits": tile_bits, "low_bits": low_bits}
+    sims = {}
+    try:
+        for dt in ("c64", "c128"):
+            s = Q.Simulator(n, dt, tile_bits=tile_bits, low_bits=low_bits, fusion=Q.QTASK_FUSE_DENSE,
+                            fuse_width=k, **common)
+            sims[dt] = s
+            s.build(wl.nets)
+            st = s.update()
+            tflops = st["mfma_flops"] / (st["kernel_ms"] * 1e-3) / 1e12
+            out[dt] = {"full_ms": st["kernel_ms"], "passes": st["passes"],
+                       "gbs": st["bytes"] / (st["kernel_ms"] * 1e-3) / 1e9,
+                       "mfma_flops": st["mfma_flops"], "mfma_tflops": tflops,
+                       "frac_of_mfma_peak": tflops / MFMA_PEAK_TFLOPS[dt]}
+        a, b = sims["c128"], sims["c64"]
+        inner = Q.qtask_inner(a.h, b.h)
+        out["fidelity_c64_vs_c128"] = abs(inner) ** 2 / (Q.qtask_norm(a.h) * Q.qtask_norm(b.h))
+        # max-abs over a sample: the first amplitudes, and 4096 spread over the rest
+        err = 0.0
+        for lo in range(0, sample, 1 << 16):
+            err = max(err, float(np.max(np.abs(a.state(lo, 1 << 16) - b.state(lo, 1 << 16).astype(np.complex128)))))
+        for i in np.linspace(sample, (1 << n) - 1, 4096).astype(np.int64):
+            err = max(err, float(abs(a.state(int(i), 1)[0] - complex(b.state(int(i), 1)[0]))))
+        out["max_abs_c64_vs_c128_sampled"] = err
+        out["sample"] = "first %d amplitudes and 4096 spread over the rest" % sample
+    finally:
+        for s in sims.values():
+            s.close()
+    s = Q.Simulator(n, "c64", autotune=1, **common)
+    try:
+        s.build(wl.nets)
+        st = s.update()
+        o = Q.qtask_get_opts(s.h)
+        out["gate_list_c64"] = {"full_ms": st["kernel_ms"], "passes": st["passes"],
+                                "gbs": st["bytes"] / (st["kernel_ms"] * 1e-3) / 1e9,
+                                "tile_bits": o.tile_bits, "low_bits": o.low_bits}
+    finally:
+        s.close()
+    return out
+
+
 def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
     """Time the CPU oracle (all host threads) on the first nets of the same
     circuit, adding nets until about min_s seconds of work."""
@@ -291,6 +345,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-append", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
+    ap.add_argument("--fused-levels", type=int, default=300, help="depth of the fused-unitary leg")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -343,6 +400,15 @@ def main():
         log("28-qubit complex128 full simulation: %.1f ms, %.0f GB/s (%.2f of peak)" % (
             large["full_ms"], large["gbs"], large["frac_of_peak"]))
 
+    fused = None
+    if not args.no_fused:
+        fused = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels)
+        log("%d-qubit fused k=5: complex64 %.0f ms (%.1f TFLOP/s on the matrix cores), complex128 %.0f ms "
+            "(%.1f TFLOP/s); fidelity %.12f, sampled max-abs %.2e; gate-list complex64 %.0f ms" % (
+                fused["qubits"], fused["c64"]["full_ms"], fused["c64"]["mfma_tflops"], fused["c128"]["full_ms"],
+                fused["c128"]["mfma_tflops"], fused["fidelity_c64_vs_c128"], fused["max_abs_c64_vs_c128_sampled"],
+                fused["gate_list_c64"]["full_ms"]))
+
     per_gate = r128["pass_bytes"] * r128["passes_per_full"] / W.count_gates(nets)
     cpu = None if args.no_cpu else cpu_baseline(W, wl, per_gate)
 
@@ -394,6 +460,7 @@ def main():
                      "scope": "every pass launch of the timed steps (incremental and full), complex128"},
         "append_protocol": append,
         "large_state": large,
+        "fused_dense": fused,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -15,6 +15,7 @@ WRITE_SIZE``, one pass each) of the same benchmark command, and writes
 
 Usage::
 
+    python -m paper_2210_01076_amd.profiling mfma --trace DIR --pmc DIR --kernel NAME --out-txt FILE
     python -m paper_2210_01076_amd.profiling --trace DIR --fetch DIR --write DIR \\
         --bench-json FILE --counter-bench-json FILE --out-txt FILE --out-json FILE \\
         --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
@@ -27,6 +28,7 @@ import glob
 import hashlib
 import json
 import os
+import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -160,7 +162,73 @@ def summarize(trace, fetch, write, bench_json, counter_bench_json, copy_bytes, c
     return rec, "\n".join(lines) + "\n"
 
 
+MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
+
+
+def summarize_mfma(trace, pmc, kernel, command, cus=256, simds=4, xcds=8):
+    """Matrix-core figures of one kernel: average duration from the trace,
+    MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_* (units of 512 flops), and the
+    busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (cycles x CUs x SIMDs), where the
+    kernel's cycles are GRBM_GUI_ACTIVE / XCDs (the GRBM counter is summed
+    over the eight XCDs)."""
+    stats = kernel_stats(trace)
+    durs = []
+    with open(_one(trace, "kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            if _short(r["Kernel_Name"]) == kernel:
+                durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    per = defaultdict(list)
+    with open(_one(pmc, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if _short(r["Kernel_Name"]) == kernel:
+                per[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    avg = {k: _mean(v) for k, v in per.items()}
+    prec = "F64" if "<double" in kernel else "F32"
+    flops = avg.get("SQ_INSTS_VALU_MFMA_MOPS_" + prec, float("nan")) * 512.0
+    dur_ns = _mean(durs)
+    tflops = flops / dur_ns / 1e3
+    cycles = avg.get("GRBM_GUI_ACTIVE", float("nan")) / xcds
+    busy = avg.get("SQ_VALU_MFMA_BUSY_CYCLES", float("nan")) / (cycles * cus * simds)
+    rec = {"kernel": kernel, "dispatches_traced": len(durs), "avg_duration_us": dur_ns / 1e3,
+           "mfma_flops_per_dispatch": flops, "mfma_tflops": tflops, "peak_tflops": MFMA_PEAK_TFLOPS[prec],
+           "frac_of_peak": tflops / MFMA_PEAK_TFLOPS[prec], "mfma_busy_frac": busy, "counters": avg,
+           "command": command}
+    lines = ["# %s -- matrix-core use" % kernel, ""]
+    for k, v in command.items():
+        lines.append("%s: %s" % (k, v))
+    lines += ["", "kernel statistics (rocprofv3 --stats):", "%-44s %7s %12s %12s %6s" % (
+        "kernel", "calls", "avg_us", "total_ms", "pct")]
+    for name, calls, a, tot, p in stats[:8]:
+        lines.append("%-44s %7d %12.2f %12.2f %6.2f" % (name[:44], calls, a / 1e3, tot / 1e6, p))
+    lines += ["", "%s: %d dispatches traced, avg %.2f us" % (kernel, len(durs), dur_ns / 1e3),
+              "counters per dispatch (averages):"]
+    for k in sorted(avg):
+        lines.append("  %-32s %.6g" % (k, avg[k]))
+    lines += ["MFMA flops per dispatch (MOPS x 512): %.4g" % flops,
+              "achieved: %.1f TFLOP/s = %.3f of the %.1f TFLOP/s dense %s matrix peak" % (
+                  tflops, tflops / MFMA_PEAK_TFLOPS[prec], MFMA_PEAK_TFLOPS[prec], prec),
+              "kernel cycles: GRBM_GUI_ACTIVE / %d XCDs = %.4g (%.2f GHz over the traced duration)" % (
+                  xcds, cycles, cycles / dur_ns),
+              "MFMA busy: SQ_VALU_MFMA_BUSY_CYCLES / (cycles x %d CUs x %d SIMDs) = %.3f" % (cus, simds, busy)]
+    return rec, "\n".join(lines) + "\n"
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "mfma":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("mode")
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--pmc", required=True)
+        ap.add_argument("--kernel", required=True)
+        ap.add_argument("--cmd-trace", default="")
+        ap.add_argument("--cmd-pmc", default="")
+        ap.add_argument("--out-txt", required=True)
+        a = ap.parse_args()
+        rec, txt = summarize_mfma(a.trace, a.pmc, a.kernel, {"trace": a.cmd_trace, "pmc": a.cmd_pmc})
+        with open(a.out_txt, "w") as f:
+            f.write(txt)
+        print(txt)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
