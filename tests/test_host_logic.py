@@ -156,6 +156,35 @@ def test_planner_emulation_matches_oracle(n, b, c, seed, fam):
     assert sum(seg["gates"] for seg in dump["segments"]) == W.count_gates(nets)
 
 
+def test_planner_factors_diagonal_phases():
+    """Every one-qubit diagonal runs as diag(1, p); each segment that had one
+    ends with a single scalar op holding the product of the factored d0, and
+    the plan still reproduces the oracle's state."""
+    n = 9
+    nets = W.layered_circuit(n, 8, 31)
+    with plan_only(n, tile_bits=6, low_bits=2, ckpt_interval=3) as sim:
+        sim.build(nets)
+        sim.update()
+        dump = sim.dump()
+    kop_d1, kop_p1, kop_gph = 2, 14, 16
+    for seg in dump["segments"]:
+        ops = [op for p in seg["passes"] for st in p["stages"] for op in st["ops"]]
+        assert not any(op["kop"] == kop_d1 for op in ops)
+        gph = [op for op in ops if op["kop"] == kop_gph]
+        # the layered family has no native phase gates: every P1 is a factored RZ
+        if not any(op["kop"] == kop_p1 for op in ops):
+            assert not gph
+            continue
+        assert len(gph) == 1 and gph[0]["q"] == []
+        assert seg["passes"][-1]["stages"][-1]["ops"][-1]["kop"] == kop_gph
+        g = complex(*gph[0]["m"][0])
+        assert abs(abs(g) - 1.0) < 1e-13
+        for op in ops:
+            if op["kop"] == kop_p1:
+                assert complex(*op["m"][0]) == 1 and abs(abs(complex(*op["m"][3])) - 1.0) < 1e-13
+    np.testing.assert_allclose(emulate(dump, n), oracle.simulate(n, nets), atol=1e-12)
+
+
 @pytest.mark.parametrize("k,b", [(4, 10), (5, 10), (6, 11), (5, 12), (4, 6)])
 def test_planner_dense_fusion_emulation(k, b):
     n = 13
