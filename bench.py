@@ -190,6 +190,30 @@ def run_serving(Q, W, dtype, specs, keep_n=20):
         Q.qtask_server_destroy(sv)
 
 
+def run_serving_sweep(Q, W, dtype, rates, seed=4242):
+    """Latency against offered load: one request (1-3 edits) per session,
+    arriving as one Poisson stream of the given aggregate rate (requests/s)
+    spread over the sessions in a random order."""
+    import numpy as np
+
+    base = W.serving_sessions(requests=1)
+    curve = []
+    for rate in rates:
+        rng = np.random.default_rng(seed)
+        times = np.cumsum(rng.exponential(1.0 / rate, size=len(base)))
+        order = rng.permutation(len(base))
+        for k, i in enumerate(order):
+            base[i].arrivals = [float(times[k])]
+        res, _ = run_serving(Q, W, dtype, base, keep_n=0)
+        point = {"offered_per_s": rate, "served_per_s": res["updates_per_s"], "latency_ms_p50": res["latency_ms_p50"],
+                 "latency_ms_p99": res["latency_ms_p99"], "service_ms_p50": res["service_ms_p50"],
+                 "failed": res["failed"], "requests": res["requests"]}
+        log("serving sweep %s offered %.0f/s: served %.1f/s, p50 %.0f ms, p99 %.0f ms" % (
+            dtype, rate, point["served_per_s"], point["latency_ms_p50"], point["latency_ms_p99"]))
+        curve.append(point)
+    return curve
+
+
 def run_append(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10):
     """The paper's append protocol: build the circuit net by net and update
     the state after each; every `every` nets also time a full
@@ -346,6 +370,8 @@ def main():
     ap.add_argument("--no-append", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="only the serving latency-throughput sweep (several minutes), printed as one JSON line")
     ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
     ap.add_argument("--fused-levels", type=int, default=300, help="depth of the fused-unitary leg")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
@@ -357,6 +383,15 @@ def main():
 
     from paper_2210_01076_amd import qtask as Q
     from paper_2210_01076_amd import workloads as W
+
+    if args.serving_sweep:
+        sweep = {"metric": "serving request latency against offered load", "unit": "ms",
+                 "workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels, "
+                             "one request of 1-3 edits each, Poisson arrivals at the offered rate",
+                 "c64": run_serving_sweep(Q, W, "c64", [8, 16, 32, 48]),
+                 "c128": run_serving_sweep(Q, W, "c128", [8, 16, 24])}
+        print(json.dumps(sweep))
+        return
 
     copy_gbs = Q.qtask_copy_bandwidth(0, 1 << 30, 20)
     log("copy kernel ceiling %.1f GB/s" % copy_gbs)
