@@ -271,8 +271,8 @@ def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 <<
     """Configuration 3: the layered family at 30 qubits with every stage fused
     into a dense k-qubit unitary on the matrix cores, complex64 (renormalised
     at every 50-level segment end) against complex128, both fused; then the
-    same circuit on the gate-list path (complex64, autotuned) for
-    comparison."""
+    same circuit in complex64 with the autotuner choosing the tile shape and
+    whether to fuse (and how wide) for comparison."""
     import numpy as np
 
     wl = W.config(3, n=n, levels=levels)
@@ -310,9 +310,10 @@ def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 <<
         s.build(wl.nets)
         st = s.update()
         o = Q.qtask_get_opts(s.h)
-        out["gate_list_c64"] = {"full_ms": st["kernel_ms"], "passes": st["passes"],
+        out["autotuned_c64"] = {"full_ms": st["kernel_ms"], "passes": st["passes"],
                                 "gbs": st["bytes"] / (st["kernel_ms"] * 1e-3) / 1e9,
-                                "tile_bits": o.tile_bits, "low_bits": o.low_bits}
+                                "tile_bits": o.tile_bits, "low_bits": o.low_bits,
+                                "fusion": {0: "auto", 1: "none", 2: "dense"}[o.fusion], "fuse_width": o.fuse_width}
     finally:
         s.close()
     return out
@@ -439,10 +440,10 @@ def main():
     if not args.no_fused:
         fused = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels)
         log("%d-qubit fused k=5: complex64 %.0f ms (%.1f TFLOP/s on the matrix cores), complex128 %.0f ms "
-            "(%.1f TFLOP/s); fidelity %.12f, sampled max-abs %.2e; gate-list complex64 %.0f ms" % (
+            "(%.1f TFLOP/s); fidelity %.12f, sampled max-abs %.2e; autotuned complex64 %.0f ms (%s)" % (
                 fused["qubits"], fused["c64"]["full_ms"], fused["c64"]["mfma_tflops"], fused["c128"]["full_ms"],
                 fused["c128"]["mfma_tflops"], fused["fidelity_c64_vs_c128"], fused["max_abs_c64_vs_c128_sampled"],
-                fused["gate_list_c64"]["full_ms"]))
+                fused["autotuned_c64"]["full_ms"], fused["autotuned_c64"]["fusion"]))
 
     per_gate = r128["pass_bytes"] * r128["passes_per_full"] / W.count_gates(nets)
     cpu = None if args.no_cpu else cpu_baseline(W, wl, per_gate)

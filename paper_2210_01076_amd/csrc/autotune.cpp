@@ -1,13 +1,16 @@
-// Autotuner for the tile shape (tile bits b, contiguous low bits c).
+// Autotuner for the tile shape (tile bits b, contiguous low bits c) and, under
+// QTASK_FUSE_AUTO, the fusion mode and width k.
 //
 // The paper leaves the block size to the user because the best value depends
 // on the circuit and the machine (Section IV-F).  Here the library measures
 // instead: at the first update of a session it plans the circuit's first
-// levels with every candidate shape, runs each plan on the device (twice,
-// keeping the second timing), and keeps the shape with the lowest time per
-// gate.  The pick is cached per (device, state qubits, dtype, fusion, gate
-// mix) and frozen for the session, so every later plan of the session, full
-// or incremental, uses the same shape and results stay bitwise reproducible.
+// levels with every candidate, runs each plan on the device (twice, keeping
+// the second timing, unless the first is already well behind), and keeps the
+// fastest.  The pick is cached per (device, state qubits, dtype, requested
+// fusion mode and width, gate mix) and frozen for the session, so every later
+// plan of the session, full or incremental, uses the same shape and results
+// stay bitwise reproducible.
+#include <array>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -19,7 +22,7 @@ namespace qtask {
 
 namespace {
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int, uint64_t>, std::pair<int, int>> g_cache;
+std::map<std::tuple<int, int, int, int, int, uint64_t>, std::array<int, 4>> g_cache;  // b, c, fusion, k
 
 uint64_t mix_signature(const std::vector<LGate> &ops) {
     // histogram of op classes in tenths of the total
@@ -53,29 +56,42 @@ int Session::autotune() {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find(key);
         if (it != g_cache.end()) {
-            opts.tile_bits = it->second.first;
-            opts.low_bits = it->second.second;
+            opts.tile_bits = it->second[0];
+            opts.low_bits = it->second[1];
+            opts.fusion = it->second[2];
+            opts.fuse_width = it->second[3];
             return QTASK_OK;
         }
     }
     rc = ensure_state();
     if (rc != QTASK_OK) return rc;
-    std::vector<std::pair<int, int>> cand;
+    // candidates: tile shape (b, c) at the session's fusion mode; under
+    // QTASK_FUSE_AUTO also every stage fused into a dense k-qubit unitary on
+    // the matrix cores, k = 4..6 (the fusion width is tuned with the shape)
+    struct Cand {
+        int b, c, fusion, k;
+    };
+    std::vector<Cand> cand;
     for (int b : {10, 11, 12, 13})
         for (int c : {3, 4, 5, 6, 8})
             if (b <= n_int && c <= b - 3 && (opts.fusion != QTASK_FUSE_DENSE || b - opts.fuse_width >= 4))
-                cand.emplace_back(b, c);
-    if (cand.empty()) cand.emplace_back(std::min(opts.tile_bits, n_int), std::min(opts.low_bits, n_int));
+                cand.push_back({b, c, opts.fusion, opts.fuse_width});
+    if (opts.fusion == QTASK_FUSE_AUTO)
+        for (int k = 4; k <= QK_MAX_DENSE_K; ++k)
+            for (int b : {10, 11, 12, 13})
+                if (b <= n_int && b - k >= 4) cand.push_back({b, 4, QTASK_FUSE_DENSE, k});
+    if (cand.empty())
+        cand.push_back({std::min(opts.tile_bits, n_int), std::min(opts.low_bits, n_int), opts.fusion, opts.fuse_width});
     double best_t = 1e300;
-    std::pair<int, int> best = cand.front();
+    Cand best = cand.front();
     for (const auto &bc : cand) {
         PlanParams pp;
         pp.n = n_int;
-        pp.b = bc.first;
-        pp.c = bc.second;
+        pp.b = bc.b;
+        pp.c = bc.c;
         pp.dtype = dtype;
-        pp.fusion = opts.fusion;
-        pp.fuse_k = opts.fuse_width;
+        pp.fusion = bc.fusion;
+        pp.fuse_k = bc.k;
         pp.swz = dtype == QTASK_C128 ? 4 : 5;
         SegmentPlan sp;
         try {
@@ -87,6 +103,8 @@ int Session::autotune() {
         if (rc != QTASK_OK) return rc;
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == QTASK_OK; ++rep) {
+            // a first run well behind the best so far cannot win: skip the second
+            if (rep == 1 && ms > 1.3 * best_t) break;
             if (hipEventRecord(ev0_, stream) != hipSuccess) rc = QTASK_E_DEVICE;
             const char *blob = static_cast<const char *>(sp.dev);
             for (size_t p = 0; p < sp.passes.size() && rc == QTASK_OK; ++p) {
@@ -117,10 +135,12 @@ int Session::autotune() {
             best = bc;
         }
     }
-    opts.tile_bits = best.first;
-    opts.low_bits = best.second;
+    opts.tile_bits = best.b;
+    opts.low_bits = best.c;
+    opts.fusion = best.fusion;
+    opts.fuse_width = best.k;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[key] = best;
+    g_cache[key] = {best.b, best.c, best.fusion, best.k};
     return QTASK_OK;
 }
 
