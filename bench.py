@@ -264,6 +264,46 @@ def run_large(Q, W, n=28, levels=100, dtype="c128"):
             "tile_bits": o.tile_bits, "low_bits": o.low_bits}
 
 
+def run_ladder32(Q, W, levels=60, edits=6, tile_bits=13, low_bits=4, ckpt_nets=45):
+    """Configuration 5 at reduced depth: 32 qubits in complex128 (a 64 GiB
+    state plus two 64 GiB checkpoints), rotations and controlled-phase
+    ladders, then single-gate inserts alternating between gates inside one
+    tile (all qubits below b) and gates with a qubit at or above b.  Each
+    update is timed, then a full re-simulation of the same circuit, and the
+    two states are compared by hash."""
+    n = 32
+    wl = W.config(5, levels=levels, batches=1)
+    nets = [list(x) for x in wl.nets]
+    batches = W.split_edits(n, nets, 5005, edits, tile_bits)
+    s = Q.Simulator(n, "c128", device=0, ckpt_interval=ckpt_nets, max_ckpts=2, tile_bits=tile_bits,
+                    low_bits=low_bits)
+    try:
+        s.build(nets)
+        st = s.update()
+        full0 = st
+        rows = []
+        for i, batch in enumerate(batches):
+            for e in batch:
+                W.apply_edit(nets, e)
+                s.apply_edit(e)
+            st = s.update()
+            h = s.hash()
+            sf = s.update(full=True)
+            rows.append({"high": i % 2 == 1, "gate": batch[0].gate[0], "qubits": list(batch[0].gate[1]),
+                         "mode": st["mode"], "first_level": st["first_level"], "inc_ms": st["kernel_ms"],
+                         "full_ms": sf["kernel_ms"], "equal": h == s.hash()})
+            log("ladder-32 edit %d (%s on %s): mode %d from net %d, %.0f ms vs full %.0f ms" % (
+                i, batch[0].gate[0], batch[0].gate[1], st["mode"], st["first_level"], st["kernel_ms"], sf["kernel_ms"]))
+    finally:
+        s.close()
+    gbs = full0["bytes"] / (full0["kernel_ms"] * 1e-3) / 1e9
+    sp = [r["full_ms"] / r["inc_ms"] for r in rows]
+    return {"qubits": n, "levels": levels, "nets": len(wl.nets), "dtype": "c128", "state_gib": 64,
+            "tile_bits": tile_bits, "low_bits": low_bits, "ckpt_nets": ckpt_nets,
+            "full_ms": full0["kernel_ms"], "passes": full0["passes"], "gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+            "edits": rows, "speedup_p50": pct(sp, 50), "mismatches": sum(not r["equal"] for r in rows)}
+
+
 MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # dense FP32 / FP64 matrix-core peaks
 
 
@@ -371,6 +411,8 @@ def main():
     ap.add_argument("--no-append", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--ladder32", action="store_true",
+                    help="only the 32-qubit controlled-phase ladder with single-gate edits (about a minute)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only the serving latency-throughput sweep (several minutes), printed as one JSON line")
     ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
@@ -384,6 +426,11 @@ def main():
 
     from paper_2210_01076_amd import qtask as Q
     from paper_2210_01076_amd import workloads as W
+
+    if args.ladder32:
+        print(json.dumps({"metric": "32-qubit full simulation GB/s; single-gate update vs full re-simulation",
+                          "ladder32": run_ladder32(Q, W)}))
+        return
 
     if args.serving_sweep:
         sweep = {"metric": "serving request latency against offered load", "unit": "ms",

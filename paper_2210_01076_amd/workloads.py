@@ -259,6 +259,49 @@ def modifier_batches(n: int, nets: List[Net], seed: int, batches: int,
     return out
 
 
+def split_edits(n: int, nets: List[Net], seed: int, count: int, b: int,
+                kinds: Sequence[str] = ("rx", "ry", "rz", "cp")) -> List[List[Edit]]:
+    """``count`` single-gate inserts at uniform nets, alternating between
+    gates whose qubits all lie below ``b`` (inside one tile) and gates with a
+    qubit at or above ``b``.  The qubits come from the net's free qubits when
+    enough are free; otherwise the gate goes into a new net right after it.
+    Drawn against a private copy of the circuit, like modifier_batches."""
+    rng = np.random.default_rng(seed)
+    model = [list(net) for net in nets]
+    out: List[List[Edit]] = []
+    for i in range(count):
+        high = i % 2 == 1
+        li = int(rng.integers(len(model)))
+        kind = str(kinds[int(rng.integers(len(kinds)))])
+        k = N_QUBITS[kind]
+        free = _free_qubits(n, model[li])
+        pool_lo = [q for q in range(b)]
+        pool_hi = [q for q in range(b, n)]
+        cand_lo = [q for q in free if q < b]
+        cand_hi = [q for q in free if q >= b]
+        new_net = False
+        if high and cand_hi and len(free) >= k:
+            q0 = cand_hi[int(rng.integers(len(cand_hi)))]
+            rest = [q for q in free if q != q0]
+        elif not high and len(cand_lo) >= k:
+            q0, rest = None, cand_lo
+        else:
+            new_net = True
+            if high:
+                q0 = pool_hi[int(rng.integers(len(pool_hi)))]
+                rest = [q for q in range(n) if q != q0]
+            else:
+                q0, rest = None, pool_lo
+        if q0 is None:
+            qs = [rest[int(j)] for j in rng.choice(len(rest), size=k, replace=False)]
+        else:
+            qs = [q0] + [rest[int(j)] for j in rng.choice(len(rest), size=k - 1, replace=False)]
+        e = Edit("insert", li, _gate(rng, kind, qs), new_net=new_net)
+        apply_edit(model, e)
+        out.append([e])
+    return out
+
+
 # --------------------------------------------------------------------------
 # the benchmark configurations
 # --------------------------------------------------------------------------
