@@ -305,6 +305,63 @@ struct Packer {
         }
     }
 
+    // Ops of `rem` (in order) that a pass over qubit set Q can apply: an op
+    // runs when its qubits lie in Q and no earlier deferred op shares one.
+    static size_t count_applicable(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t Q,
+                                   size_t limit) {
+        uint64_t blocked = 0;
+        size_t cnt = 0;
+        for (size_t i = 0; i < rem.size() && i < limit; ++i) {
+            const uint64_t m = mask[rem[i]];
+            if ((m & blocked) || (m & ~Q)) blocked |= m;
+            else ++cnt;
+        }
+        return cnt;
+    }
+
+    // First fit in program order: each pending op extends Q while it fits.
+    uint64_t first_fit_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t low) const {
+        uint64_t Q = low, blocked = 0;
+        for (size_t idx : rem) {
+            const uint64_t m = mask[idx];
+            if (m & blocked) { blocked |= m; continue; }
+            if (popc(Q | m) <= pp.b) Q |= m;
+            else blocked |= m;
+        }
+        return Q;
+    }
+
+    // Gain-driven choice: grow Q by the qubits of one of the first pending
+    // ops that are not yet applicable, picking the addition that makes the
+    // most ops of the look-ahead window applicable per added qubit.
+    uint64_t gain_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t low) const {
+        constexpr size_t kWindow = 128, kCands = 24;
+        uint64_t Q = low;
+        std::vector<uint64_t> cands;
+        while (popc(Q) < pp.b) {
+            cands.clear();
+            uint64_t blocked = 0;
+            for (size_t i = 0; i < rem.size() && cands.size() < kCands; ++i) {
+                const uint64_t m = mask[rem[i]];
+                const uint64_t add = m & ~Q;
+                if (!add) continue;
+                if (!(m & blocked) && popc(Q | add) <= pp.b &&
+                    std::find(cands.begin(), cands.end(), add) == cands.end())
+                    cands.push_back(add);
+                blocked |= m;
+            }
+            if (cands.empty()) break;
+            uint64_t best = cands.front();
+            double best_v = -1;
+            for (uint64_t add : cands) {
+                const double v = double(count_applicable(mask, rem, Q | add, kWindow)) / popc(add);
+                if (v > best_v) { best_v = v; best = add; }
+            }
+            Q |= best;
+        }
+        return Q;
+    }
+
     std::vector<PPass> pack_passes(const std::vector<LGate> &ops) const {
         // keep room for a three-qubit gate on qubits above the low bits, so
         // every pass can take at least the first pending gate
@@ -318,18 +375,28 @@ struct Packer {
         std::vector<size_t> take, left;
         take.reserve(ops.size());
         left.reserve(ops.size());
+        auto fill = [&](uint64_t Q) {
+            for (int q = 0; q < pp.n && popc(Q) < pp.b; ++q) Q |= uint64_t(1) << q;
+            return Q;
+        };
         while (!rem.empty()) {
-            uint64_t Q = low, blocked = 0;
+            // each pass takes the better of two qubit sets: first fit in
+            // program order (which always takes the first pending op) and
+            // the gain-driven choice (far fewer passes on layered circuits)
+            const uint64_t Qf = fill(first_fit_set(mask, rem, low));
+            const uint64_t Qg = fill(gain_set(mask, rem, low));
+            const size_t nf = count_applicable(mask, rem, Qf, rem.size());
+            const size_t ng = count_applicable(mask, rem, Qg, rem.size());
+            const uint64_t Q = ng > nf ? Qg : Qf;
             take.clear();
             left.clear();
+            uint64_t blocked = 0;
             for (size_t idx : rem) {
                 const uint64_t m = mask[idx];
-                if (m & blocked) { blocked |= m; left.push_back(idx); continue; }
-                if (popc(Q | m) <= pp.b) { Q |= m; take.push_back(idx); }
-                else { blocked |= m; left.push_back(idx); }
+                if ((m & blocked) || (m & ~Q)) { blocked |= m; left.push_back(idx); }
+                else take.push_back(idx);
             }
             if (take.empty()) throw std::logic_error("planner made no progress");
-            for (int q = 0; q < pp.n && popc(Q) < pp.b; ++q) Q |= uint64_t(1) << q;
             PPass ps;
             ps.qmask = Q;
             for (int q = 0; q < pp.n; ++q)
