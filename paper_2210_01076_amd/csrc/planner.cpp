@@ -200,22 +200,23 @@ struct Packer {
         // packed from gates above them when there are any; the others wait.
         const uint32_t low_mask = (1u << std::min(coalesce_bits(), pp.b - QK_G)) - 1;
         bool first = true;
+        const std::vector<uint64_t> mask64(tmask.begin(), tmask.end());
+        auto fill = [&](uint64_t S) {
+            for (int p = pp.b - 1; p >= 0 && popc(S) < W; --p) S |= uint64_t(1) << p;
+            return S;
+        };
+        std::vector<size_t> take, left;
         while (!rem.empty()) {
-            uint32_t S = 0, blocked = first ? low_mask : 0;
-            std::vector<size_t> take, left;
-            for (size_t idx : rem) {
-                const uint32_t m = tmask[idx];
-                if (m & blocked) { blocked |= m; left.push_back(idx); continue; }
-                if (popc(S | m) <= W) { S |= m; take.push_back(idx); }
-                else { blocked |= m; left.push_back(idx); }
-            }
+            // the better of first fit and the gain-driven choice, as for passes
+            const uint64_t forbid = first ? low_mask : 0;
+            const uint64_t S = choose_set(mask64, rem, 0, W, forbid, fill);
+            split_ops(mask64, rem, S, forbid, take, left);
             if (take.empty() && first) {
                 first = false;
                 continue;  // every pending gate touches the low bits
             }
             first = false;
             if (take.empty()) throw std::logic_error("stage packing made no progress");
-            for (int p = pp.b - 1; p >= 0 && popc(S) < W; --p) S |= 1u << p;
             PStage st;
             for (int p = 0; p < pp.b; ++p)
                 if ((S >> p) & 1) st.tbits.push_back(p);
@@ -305,11 +306,16 @@ struct Packer {
         }
     }
 
-    // Ops of `rem` (in order) that a pass over qubit set Q can apply: an op
-    // runs when its qubits lie in Q and no earlier deferred op shares one.
+    // Packing a pass (a qubit set of at most b qubits) and packing a stage
+    // (a set of at most QK_G tile bits) are the same problem over bit masks:
+    // pick a set, then run every pending op whose bits lie in it and that no
+    // earlier deferred op blocks.  `forbid` bits may not join the set (the
+    // first stage keeps the lowest tile bits on the lanes).
+
+    // Ops of `rem` (in order) that a set Q can apply.
     static size_t count_applicable(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t Q,
-                                   size_t limit) {
-        uint64_t blocked = 0;
+                                   uint64_t forbid, size_t limit) {
+        uint64_t blocked = forbid;
         size_t cnt = 0;
         for (size_t i = 0; i < rem.size() && i < limit; ++i) {
             const uint64_t m = mask[rem[i]];
@@ -319,33 +325,35 @@ struct Packer {
         return cnt;
     }
 
-    // First fit in program order: each pending op extends Q while it fits.
-    uint64_t first_fit_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t low) const {
-        uint64_t Q = low, blocked = 0;
+    // First fit in program order: each pending op extends the set while it fits.
+    static uint64_t first_fit_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
+                                  int cap, uint64_t forbid) {
+        uint64_t Q = start, blocked = forbid;
         for (size_t idx : rem) {
             const uint64_t m = mask[idx];
             if (m & blocked) { blocked |= m; continue; }
-            if (popc(Q | m) <= pp.b) Q |= m;
+            if (popc(Q | m) <= cap) Q |= m;
             else blocked |= m;
         }
         return Q;
     }
 
-    // Gain-driven choice: grow Q by the qubits of one of the first pending
-    // ops that are not yet applicable, picking the addition that makes the
-    // most ops of the look-ahead window applicable per added qubit.
-    uint64_t gain_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t low) const {
+    // Gain-driven choice: grow the set by the new bits of one of the first
+    // pending ops, picking the addition that makes the most ops of the
+    // look-ahead window applicable per added bit.
+    static uint64_t gain_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
+                             int cap, uint64_t forbid) {
         constexpr size_t kWindow = 128, kCands = 24;
-        uint64_t Q = low;
+        uint64_t Q = start;
         std::vector<uint64_t> cands;
-        while (popc(Q) < pp.b) {
+        while (popc(Q) < cap) {
             cands.clear();
-            uint64_t blocked = 0;
+            uint64_t blocked = forbid;
             for (size_t i = 0; i < rem.size() && cands.size() < kCands; ++i) {
                 const uint64_t m = mask[rem[i]];
                 const uint64_t add = m & ~Q;
                 if (!add) continue;
-                if (!(m & blocked) && popc(Q | add) <= pp.b &&
+                if (!(m & blocked) && popc(Q | add) <= cap &&
                     std::find(cands.begin(), cands.end(), add) == cands.end())
                     cands.push_back(add);
                 blocked |= m;
@@ -354,12 +362,36 @@ struct Packer {
             uint64_t best = cands.front();
             double best_v = -1;
             for (uint64_t add : cands) {
-                const double v = double(count_applicable(mask, rem, Q | add, kWindow)) / popc(add);
+                const double v = double(count_applicable(mask, rem, Q | add, forbid, kWindow)) / popc(add);
                 if (v > best_v) { best_v = v; best = add; }
             }
             Q |= best;
         }
         return Q;
+    }
+
+    // The better of the two sets (more ops applicable), after `fill` tops it up.
+    template <typename Fill>
+    static uint64_t choose_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
+                               int cap, uint64_t forbid, Fill fill) {
+        const uint64_t Qf = fill(first_fit_set(mask, rem, start, cap, forbid));
+        const uint64_t Qg = fill(gain_set(mask, rem, start, cap, forbid));
+        const size_t nf = count_applicable(mask, rem, Qf, forbid, rem.size());
+        const size_t ng = count_applicable(mask, rem, Qg, forbid, rem.size());
+        return ng > nf ? Qg : Qf;
+    }
+
+    // Split rem into the ops the set runs (take) and the rest (left).
+    static void split_ops(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t Q,
+                          uint64_t forbid, std::vector<size_t> &take, std::vector<size_t> &left) {
+        take.clear();
+        left.clear();
+        uint64_t blocked = forbid;
+        for (size_t idx : rem) {
+            const uint64_t m = mask[idx];
+            if ((m & blocked) || (m & ~Q)) { blocked |= m; left.push_back(idx); }
+            else take.push_back(idx);
+        }
     }
 
     std::vector<PPass> pack_passes(const std::vector<LGate> &ops) const {
@@ -383,19 +415,8 @@ struct Packer {
             // each pass takes the better of two qubit sets: first fit in
             // program order (which always takes the first pending op) and
             // the gain-driven choice (far fewer passes on layered circuits)
-            const uint64_t Qf = fill(first_fit_set(mask, rem, low));
-            const uint64_t Qg = fill(gain_set(mask, rem, low));
-            const size_t nf = count_applicable(mask, rem, Qf, rem.size());
-            const size_t ng = count_applicable(mask, rem, Qg, rem.size());
-            const uint64_t Q = ng > nf ? Qg : Qf;
-            take.clear();
-            left.clear();
-            uint64_t blocked = 0;
-            for (size_t idx : rem) {
-                const uint64_t m = mask[idx];
-                if ((m & blocked) || (m & ~Q)) { blocked |= m; left.push_back(idx); }
-                else take.push_back(idx);
-            }
+            const uint64_t Q = choose_set(mask, rem, low, pp.b, 0, fill);
+            split_ops(mask, rem, Q, 0, take, left);
             if (take.empty()) throw std::logic_error("planner made no progress");
             PPass ps;
             ps.qmask = Q;
