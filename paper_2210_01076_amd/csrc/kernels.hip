@@ -535,9 +535,6 @@ __device__ __forceinline__ void mfma_stage(const KStage *__restrict__ S, const R
     }
 }
 
-// One tile (number idx of the pass, or tile_list[idx]).  The first stage's
-// registers come straight from global memory, the middle stages go through
-// LDS, the last stage's registers go straight back to global memory.
 // Deposit runs of a pass, read once into scalar registers (a fixed-size
 // unrolled copy keeps them out of memory inside the tile loop).
 struct TileRuns {
@@ -567,6 +564,9 @@ __device__ __forceinline__ uint64_t tile_origin(const TileRuns &tr, uint32_t til
     return base;
 }
 
+// One tile (number idx of the pass, or tile_list[idx]).  The first stage's
+// registers come straight from global memory, the middle stages go through
+// LDS, the last stage's registers go straight back to global memory.
 template <typename R, bool MF>
 __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restrict__ tile_list, void *dst_,
                                           const void *src_, void *ckpt_, const KPass *__restrict__ P,
