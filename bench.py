@@ -307,7 +307,7 @@ def run_ladder32(Q, W, levels=60, edits=6, tile_bits=13, low_bits=4, ckpt_nets=4
 MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # dense FP32 / FP64 matrix-core peaks
 
 
-def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 << 20):
+def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 << 20, tuned=True):
     """Configuration 3: the layered family at 30 qubits with every stage fused
     into a dense k-qubit unitary on the matrix cores, complex64 (renormalised
     at every 50-level segment end) against complex128, both fused; then the
@@ -345,6 +345,8 @@ def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 <<
     finally:
         for s in sims.values():
             s.close()
+    if not tuned:
+        return out
     s = Q.Simulator(n, "c64", autotune=1, **common)
     try:
         s.build(wl.nets)
@@ -417,6 +419,9 @@ def main():
                     help="only the serving latency-throughput sweep (several minutes), printed as one JSON line")
     ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
     ap.add_argument("--fused-levels", type=int, default=300, help="depth of the fused-unitary leg")
+    ap.add_argument("--no-fused-tuned", action="store_true",
+                    help="skip the autotuned comparison run of the fused-unitary leg (its timing candidates "
+                         "would mix into a profile of the fused kernels)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -485,11 +490,13 @@ def main():
 
     fused = None
     if not args.no_fused:
-        fused = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels)
+        fused = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels, tuned=not args.no_fused_tuned)
         log("%d-qubit fused k=5: complex64 %.0f ms (%.1f TFLOP/s on the matrix cores), complex128 %.0f ms "
-            "(%.1f TFLOP/s); fidelity %.12f, sampled max-abs %.2e; autotuned complex64 %.0f ms (%s)" % (
+            "(%.1f TFLOP/s); fidelity %.12f, sampled max-abs %.2e" % (
                 fused["qubits"], fused["c64"]["full_ms"], fused["c64"]["mfma_tflops"], fused["c128"]["full_ms"],
-                fused["c128"]["mfma_tflops"], fused["fidelity_c64_vs_c128"], fused["max_abs_c64_vs_c128_sampled"],
+                fused["c128"]["mfma_tflops"], fused["fidelity_c64_vs_c128"], fused["max_abs_c64_vs_c128_sampled"]))
+        if "autotuned_c64" in fused:
+            log("autotuned complex64 on the same circuit: %.0f ms (fusion %s)" % (
                 fused["autotuned_c64"]["full_ms"], fused["autotuned_c64"]["fusion"]))
 
     per_gate = r128["pass_bytes"] * r128["passes_per_full"] / W.count_gates(nets)

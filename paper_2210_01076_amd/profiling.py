@@ -165,23 +165,29 @@ def summarize(trace, fetch, write, bench_json, counter_bench_json, copy_bytes, c
 MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
 
 
-def summarize_mfma(trace, pmc, kernel, command, cus=256, simds=4, xcds=8):
+def summarize_mfma(trace, pmc, kernel, command, last=0, cus=256, simds=4, xcds=8):
     """Matrix-core figures of one kernel: average duration from the trace,
     MFMA flops from SQ_INSTS_VALU_MFMA_MOPS_* (units of 512 flops), and the
     busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (cycles x CUs x SIMDs), where the
     kernel's cycles are GRBM_GUI_ACTIVE / XCDs (the GRBM counter is summed
     over the eight XCDs)."""
     stats = kernel_stats(trace)
-    durs = []
+    rows = []
     with open(_one(trace, "kernel_trace.csv")) as f:
         for r in csv.DictReader(f):
             if _short(r["Kernel_Name"]) == kernel:
-                durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                rows.append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    durs = [d for _, d in sorted(rows)]
     per = defaultdict(list)
     with open(_one(pmc, "counter_collection.csv")) as f:
         for r in csv.DictReader(f):
             if _short(r["Kernel_Name"]) == kernel:
-                per[r["Counter_Name"]].append(float(r["Counter_Value"]))
+                per[r["Counter_Name"]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    per = {k: [v for _, v in sorted(x)] for k, x in per.items()}
+    if last:
+        # only the measured run's dispatches: the last `last` of the kernel
+        durs = durs[-last:]
+        per = {k: v[-last:] for k, v in per.items()}
     avg = {k: _mean(v) for k, v in per.items()}
     prec = "F64" if "<double" in kernel else "F32"
     flops = avg.get("SQ_INSTS_VALU_MFMA_MOPS_" + prec, float("nan")) * 512.0
@@ -200,7 +206,8 @@ def summarize_mfma(trace, pmc, kernel, command, cus=256, simds=4, xcds=8):
         "kernel", "calls", "avg_us", "total_ms", "pct")]
     for name, calls, a, tot, p in stats[:8]:
         lines.append("%-44s %7d %12.2f %12.2f %6.2f" % (name[:44], calls, a / 1e3, tot / 1e6, p))
-    lines += ["", "%s: %d dispatches traced, avg %.2f us" % (kernel, len(durs), dur_ns / 1e3),
+    lines += ["", "%s: %d dispatches used%s, avg %.2f us" % (
+        kernel, len(durs), " (the last %d of the kernel: the measured run)" % last if last else "", dur_ns / 1e3),
               "counters per dispatch (averages):"]
     for k in sorted(avg):
         lines.append("  %-32s %.6g" % (k, avg[k]))
@@ -220,11 +227,12 @@ def main():
         ap.add_argument("--trace", required=True)
         ap.add_argument("--pmc", required=True)
         ap.add_argument("--kernel", required=True)
+        ap.add_argument("--last", type=int, default=0, help="use only the kernel's last N dispatches")
         ap.add_argument("--cmd-trace", default="")
         ap.add_argument("--cmd-pmc", default="")
         ap.add_argument("--out-txt", required=True)
         a = ap.parse_args()
-        rec, txt = summarize_mfma(a.trace, a.pmc, a.kernel, {"trace": a.cmd_trace, "pmc": a.cmd_pmc})
+        rec, txt = summarize_mfma(a.trace, a.pmc, a.kernel, {"trace": a.cmd_trace, "pmc": a.cmd_pmc}, last=a.last)
         with open(a.out_txt, "w") as f:
             f.write(txt)
         print(txt)
