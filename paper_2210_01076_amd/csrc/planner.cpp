@@ -343,7 +343,7 @@ struct Packer {
     // look-ahead window applicable per added bit.
     static uint64_t gain_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
                              int cap, uint64_t forbid) {
-        constexpr size_t kWindow = 128, kCands = 24;
+        constexpr size_t kWindow = 128, kCands = 8;
         uint64_t Q = start;
         std::vector<uint64_t> cands;
         while (popc(Q) < cap) {

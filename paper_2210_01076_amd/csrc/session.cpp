@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <future>
 #include <sstream>
 
 #include "device.h"
@@ -429,30 +430,49 @@ int Session::prepare(bool force_full) {
     const size_t S = segs_.size();
     prep_S_ = S;
     plans_.assign(S, nullptr);
+    // segments whose plan is not cached yet (one per distinct content);
+    // plan_segment is a pure function, so they are planned concurrently
+    std::vector<std::pair<uint64_t, std::vector<LGate>>> todo;
     for (size_t s = 0; s < S; ++s) {
         Seg &sg = segs_[s];
         auto kh = key_hash_.find(sg.key);
         if (kh != key_hash_.end() && plan_cache_.count(kh->second)) {
             sg.hash = kh->second;
-        } else {
-            std::vector<LGate> ops = level_ops(sg.lo, sg.hi);
-            sg.hash = segment_hash(ops, pp);
-            key_hash_[sg.key] = sg.hash;
-            if (!plan_cache_.count(sg.hash)) {
-                SegmentPlan np;
-                try {
-                    np = plan_segment(ops, pp, sg.hash);
-                } catch (const std::exception &e) {
-                    last_error = e.what();
-                    return QTASK_E_ARG;
-                }
-                int rc = upload_plan(np);
-                if (rc != QTASK_OK) return rc;
-                plan_cache_.emplace(sg.hash, std::move(np));
-            }
+            continue;
         }
-        plans_[s] = &plan_cache_.at(sg.hash);
+        std::vector<LGate> ops = level_ops(sg.lo, sg.hi);
+        sg.hash = segment_hash(ops, pp);
+        key_hash_[sg.key] = sg.hash;
+        if (plan_cache_.count(sg.hash)) continue;
+        bool dup = false;
+        for (const auto &td : todo) dup = dup || td.first == sg.hash;
+        if (!dup) todo.emplace_back(sg.hash, std::move(ops));
     }
+    constexpr size_t kPlanThreads = 8;
+    for (size_t i0 = 0; i0 < todo.size(); i0 += kPlanThreads) {
+        const size_t i1 = std::min(todo.size(), i0 + kPlanThreads);
+        std::vector<std::future<SegmentPlan>> futs;
+        for (size_t i = i0; i < i1; ++i)
+            futs.push_back(std::async(i + 1 < i1 ? std::launch::async : std::launch::deferred,
+                                      [&pp, &td = todo[i]] { return plan_segment(td.second, pp, td.first); }));
+        for (size_t i = i0; i < i1; ++i) {
+            SegmentPlan np;
+            try {
+                np = futs[i - i0].get();
+            } catch (const std::exception &e) {
+                for (size_t j = i + 1; j < i1; ++j) futs[j - i0].wait();  // no thread outlives its inputs
+                last_error = e.what();
+                return QTASK_E_ARG;
+            }
+            int rc = upload_plan(np);
+            if (rc != QTASK_OK) {
+                for (size_t j = i + 1; j < i1; ++j) futs[j - i0].wait();
+                return rc;
+            }
+            plan_cache_.emplace(todo[i].first, std::move(np));
+        }
+    }
+    for (size_t s = 0; s < S; ++s) plans_[s] = &plan_cache_.at(segs_[s].hash);
 
     // restart point: the newest valid checkpoint at or before the first
     // edited level (boundary j = the state before segment j)
