@@ -242,6 +242,82 @@ def run_append(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10):
             "mismatches": mismatches, "compared_depths": len(pairs)}
 
 
+def run_protocols(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10, mixes=50, seed=77):
+    """The paper's other incremental protocols on the same circuit (Section
+    IV): insert the nets one at a time in random order until the circuit is
+    complete, remove them one at a time in random order until it is empty,
+    and a mix of random net inserts and removals.  The state is updated after
+    every step; every `every` steps a full re-simulation is timed beside the
+    update and the two are compared bitwise."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    out = {}
+
+    def measure(name, steps):
+        s = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=ckpt_nets, tile_bits=tile_bits, low_bits=low_bits)
+        inc, pairs, mismatches = [], [], 0
+        try:
+            for i, step in enumerate(steps(s)):
+                st = s.update()
+                inc.append(st["wall_ms"])
+                if (i + 1) % every == 0:
+                    h = s.hash()
+                    sf = s.update(full=True)
+                    mismatches += int(s.hash() != h)
+                    pairs.append(sf["wall_ms"] / max(st["wall_ms"], 1e-9))
+        finally:
+            s.close()
+        out[name] = {"steps": len(inc), "update_ms_p50": pct(inc, 50), "update_ms_p99": pct(inc, 99),
+                     "speedup_p50": pct(pairs, 50) if pairs else None, "mismatches": mismatches,
+                     "compared": len(pairs)}
+
+    nets = wl.nets
+
+    def insert_random(s):
+        # nets enter in random order, each at its place among those present
+        order = rng.permutation(len(nets))
+        present = []
+        for k in order:
+            pos = int(np.searchsorted(present, k))
+            present.insert(pos, int(k))
+            s.add_level(pos)
+            for g in nets[k]:
+                s.add_gate(pos, g)
+            yield k
+
+    def remove_random(s):
+        s.build(nets)
+        s.update()
+        left = len(nets)
+        while left > 0:
+            s.remove_level(int(rng.integers(left)))
+            left -= 1
+            yield left
+
+    def mix(s):
+        s.build(nets)
+        s.update()
+        pool = list(range(len(nets)))
+        for _ in range(mixes):
+            if rng.integers(2) == 0 and len(s.levels) > 1:
+                s.remove_level(int(rng.integers(len(s.levels))))
+            else:
+                pos = int(rng.integers(len(s.levels) + 1))
+                k = pool[int(rng.integers(len(pool)))]
+                s.add_level(pos)
+                for g in nets[k]:
+                    s.add_gate(pos, g)
+            yield len(s.levels)
+
+    measure("insert_random_order", insert_random)
+    measure("remove_until_empty", remove_random)
+    measure("mixed_%d" % mixes, mix)
+    out["dtype"] = dtype
+    out["ckpt_nets"] = ckpt_nets
+    return out
+
+
 def run_large(Q, W, n=28, levels=100, dtype="c128"):
     """Full simulations of the layered family at a state far larger than the
     256 MB Infinity Cache: HBM-only throughput of the pass kernel."""
@@ -482,6 +558,14 @@ def main():
         append = run_append(Q, wl, "c128", r128["tile_bits"], r128["low_bits"])
         log("append protocol: update p50 %.2f ms, speedup vs full p50 %.1f (at full depth %.1f)" % (
             append["update_ms_p50"], append["speedup_p50"], append["speedup_at_full_depth"]))
+    protocols = None
+    if not args.no_append:
+        protocols = run_protocols(Q, wl, "c128", r128["tile_bits"], r128["low_bits"])
+        for k in ("insert_random_order", "remove_until_empty", "mixed_50"):
+            p = protocols[k]
+            log("%s: %d steps, update p50 %.2f ms p99 %.2f ms, speedup vs full p50 %s, mismatches %d" % (
+                k, p["steps"], p["update_ms_p50"], p["update_ms_p99"],
+                "%.1f" % p["speedup_p50"] if p["speedup_p50"] else "-", p["mismatches"]))
     large = None
     if not args.no_large:
         large = run_large(Q, W)
@@ -549,6 +633,7 @@ def main():
                      "block": 1 << (r128["tile_bits"] - 4),
                      "scope": "every pass launch of the timed steps (incremental and full), complex128"},
         "append_protocol": append,
+        "other_protocols": protocols,
         "large_state": large,
         "fused_dense": fused,
         "serving": serving,

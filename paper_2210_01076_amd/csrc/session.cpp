@@ -282,6 +282,15 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     if (oe < s_edit - s0) return QTASK_E_UNSUPPORTED;
     for (size_t k = 1; k <= s_edit - s0; ++k)
         if (prev_hashes_[oe - k] != segs_[s_edit - k].hash) return QTASK_E_UNSUPPORTED;
+    // the edited segment must start at the same boundary as the old one it
+    // is compared with: removing the level that ended the previous segment
+    // merges the two, and the old plan would then cover only part of the
+    // new segment (a block rewritten only by the removed level would look
+    // unchanged)
+    if ((s_edit == 0) != (oe == 0)) return QTASK_E_UNSUPPORTED;
+    if (s_edit > 0 && (prev_anchors_.size() != prev_hashes_.size() ||
+                       prev_anchors_[oe - 1] != segs_[s_edit - 1].anchor))
+        return QTASK_E_UNSUPPORTED;
     if (prev_hashes_[oe] == segs_[s_edit].hash) {
         S = BlockSet(nblocks);  // the edits cancelled out: nothing to redo
         return QTASK_OK;
@@ -731,7 +740,11 @@ int Session::finish_prepared_host() {
         if (j > prep_s0_ && prep_mode_ != 3) it->second.valid = true;
     }
     prev_hashes_.clear();
-    for (const auto &sg : segs_) prev_hashes_.push_back(sg.hash);
+    prev_anchors_.clear();
+    for (const auto &sg : segs_) {
+        prev_hashes_.push_back(sg.hash);
+        prev_anchors_.push_back(sg.anchor);
+    }
     circ.clear_edits();
     have_result_ = true;
     state_valid_ = !plan_only;
@@ -803,6 +816,7 @@ void Session::release_device() {
     key_hash_.clear();
     plans_.clear();
     prev_hashes_.clear();
+    prev_anchors_.clear();
     for (auto &kv : ckpts_) dfree(kv.second.buf.p);
     ckpts_.clear();
     dfree(state_.p);

@@ -124,6 +124,7 @@ private:
     std::unordered_map<uint64_t, SegmentPlan> plan_cache_;  // by content hash
     std::unordered_map<uint64_t, uint64_t> key_hash_;       // segment key -> content hash
     std::vector<uint64_t> prev_hashes_;                   // segment hashes at the last update
+    std::vector<uint64_t> prev_anchors_;                  // segment end anchors at the last update
     std::unordered_set<uint64_t> anchors_;
     std::unordered_map<uint64_t, Ckpt> ckpts_;            // by anchor level id
     std::unordered_map<uint64_t, size_t> slots_;          // anchor -> norm/scale slot (0: circuit end)

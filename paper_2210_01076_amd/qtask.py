@@ -429,6 +429,12 @@ class Simulator:
         self.gates.insert(index, [])
         return lid
 
+    def remove_level(self, index: int) -> None:
+        """Remove the level at position ``index`` with its gates."""
+        qtask_remove_level(self.h, self.levels[index])
+        del self.levels[index]
+        del self.gates[index]
+
     def add_gate(self, level_index: int, gate) -> int:
         kind, qs, ps = gate
         gid = qtask_insert_gate(self.h, self.levels[level_index], kind, qs, ps)

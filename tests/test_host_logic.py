@@ -320,6 +320,56 @@ def test_tracker_sound_against_oracle(seed):
                 assert st["mode"] == 2
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_tracker_sound_under_level_removal(seed):
+    """Removing whole levels, including the ones that end a segment (which
+    merges two segments): the blocks that actually change still lie inside
+    the affected set whenever the update restricts itself to it."""
+    rng = np.random.default_rng(seed)
+    n, bb, K = 7, 3, 2
+    nets = W.dense_random_circuit(n, 14, 70 + seed, kinds=("x", "cx", "z", "s", "cz", "swap", "t", "h"))
+    with plan_only(n, block_bits=bb, ckpt_interval=K, tile_bits=5, low_bits=2) as sim:
+        sim.build(nets)
+        sim.update()
+        modes = []
+        for trial in range(8):
+            if len(nets) < 2:
+                break
+            old = [list(x) for x in nets]
+            li = int(rng.integers(len(nets)))
+            del nets[li]
+            sim.remove_level(li)
+            st = sim.update()
+            modes.append(st["mode"])
+            if st["mode"] == 3:
+                a = oracle.snapshots(n, old)[-1]
+                b = oracle.snapshots(n, nets)[-1]
+                dirty = set(sim.dump()["dirty_block_list"])
+                assert oracle.changed_blocks(a, b, bb) <= dirty, (trial, li)
+            else:
+                assert st["mode"] == 2
+
+
+def test_level_removal_inside_a_segment_stays_closed():
+    """Removing a level that does not end its segment keeps the restricted
+    replay available, and its affected set covers what actually changes."""
+    n, bb = 7, 3
+    nets = [[("h", (q,), ()) for q in range(n)]]
+    nets += [[("cx", (6, 5), ())], [("z", (1,), ()), ("t", (4,), ())], [("cz", (2, 6), ())], [("s", (3,), ())],
+             [("t", (5,), ())], [("cz", (0, 4), ())], [("z", (6,), ())], [("s", (5,), ())]]
+    with plan_only(n, block_bits=bb, ckpt_interval=4, tile_bits=5, low_bits=2) as sim:
+        sim.build(nets)
+        sim.update()
+        old = [list(x) for x in nets]
+        del nets[4]
+        sim.remove_level(4)
+        st = sim.update()
+        assert st["mode"] == 3
+        dirty = set(sim.dump()["dirty_block_list"])
+        changed = oracle.changed_blocks(oracle.snapshots(n, old)[-1], oracle.snapshots(n, nets)[-1], bb)
+        assert changed and changed <= dirty and len(dirty) < 1 << (n - bb)
+
+
 def test_server_opts_and_edit_records():
     o = Q.qtask_server_opts_default()
     assert o.struct_size == Q.ctypes.sizeof(Q.qtask_server_opts)
