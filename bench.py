@@ -464,10 +464,18 @@ def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
         if time.perf_counter() - t1 >= min_s / 3:
             break
     dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": full_bytes_per_gate * gates / dt / 1e9,
         "unit": "GB/s",
         "cores": threads,
+        "cpu_model": model,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": "first %d nets (%d gates) of the %d-qubit circuit, complex128, %.1f s on %d threads; value = the "
                   "GPU plan's bytes for the same gates / oracle time" % (used, gates, wl.n, dt, threads),
