@@ -340,7 +340,7 @@ def run_large(Q, W, n=28, levels=100, dtype="c128"):
             "tile_bits": o.tile_bits, "low_bits": o.low_bits}
 
 
-def run_ladder32(Q, W, levels=60, edits=6, tile_bits=13, low_bits=4, ckpt_nets=45):
+def run_ladder32(Q, W, levels=60, edits=6, tile_bits=12, low_bits=3, ckpt_nets=45):
     """Configuration 5 at reduced depth: 32 qubits in complex128 (a 64 GiB
     state plus two 64 GiB checkpoints), rotations and controlled-phase
     ladders, then single-gate inserts alternating between gates inside one
@@ -636,7 +636,7 @@ def main():
         "c64": r64,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "qk_pass_pf<double>", "bytes_per_launch": r128["launch_bytes"],
+                     "kernel": "qk_pass<double, false>", "bytes_per_launch": r128["launch_bytes"],
                      "avg_launch_ms": r128["launch_ms"], "launches_timed": r128["launches"],
                      "block": 1 << (r128["tile_bits"] - 4),
                      "scope": "every pass launch of the timed steps (incremental and full), complex128"},

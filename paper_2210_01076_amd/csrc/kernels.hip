@@ -689,153 +689,6 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     }
 }
 
-// Persistent variant for complex128 (whose tile fills most of a CU's LDS, so
-// only two workgroups share a CU): workgroup w runs tiles w, w + stride, ...
-// and loads the first-stage registers of its next tile into a second
-// register set while it computes the current one.  The wait for those loads
-// sits just before the current tile's stores, so neither the loads nor the
-// stores of a tile stall the workgroup.
-template <typename R>
-__device__ __forceinline__ void pass_tiles_pf(uint32_t idx0, uint32_t stride, uint32_t n_idx,
-                                              const uint32_t *__restrict__ tile_list, void *dst_,
-                                              const void *src_, void *ckpt_, const KPass *__restrict__ P,
-                                              const KStage *__restrict__ stages, const KOp *__restrict__ ops,
-                                              const R *__restrict__ coefs, const uint64_t *__restrict__ store_mask,
-                                              const double *__restrict__ scale, double *__restrict__ partials,
-                                              uint32_t src_basis, uint32_t block_bits,
-                                              typename V2<R>::T *__restrict__ lds) {
-    using C = typename V2<R>::T;
-    if (idx0 >= n_idx) return;
-    const uint32_t t = threadIdx.x;
-    const uint32_t n_thr = P->n_thr;
-    const uint32_t ns = P->stage_count;
-    const KStage *__restrict__ S0 = stages + P->stage_begin;
-    const KStage *__restrict__ SL = S0 + (ns - 1);
-    const uint64_t gt0 = thr_glb(S0, t);
-    const uint64_t gtl = thr_glb(SL, t);
-    const TileRuns tr = load_runs(P);
-    auto tile_base = [&](uint32_t idx) {
-        return tile_origin(tr, tile_list ? tile_list[idx] : idx);
-    };
-    C pa[NR];
-    auto fetch = [&](uint32_t idx) {
-        uint64_t g[NR];
-        reg_goffs(S0, tile_base(idx) | gt0, g);
-        if (src_basis) {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                pa[i].x = g[i] == 0 ? R(1) : R(0);
-                pa[i].y = R(0);
-            }
-        } else {
-            const C *src = static_cast<const C *>(src_);
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                const C y = src[g[i]];
-                pa[i].x = y.x;
-                pa[i].y = y.y;
-            }
-        }
-    };
-    fetch(idx0);
-    const KOp op0 = ops[S0->op_begin];
-    for (uint32_t idx = idx0; idx < n_idx; idx += stride) {
-        C a[NR];
-#pragma unroll
-        for (int i = 0; i < NR; ++i) { a[i].x = pa[i].x; a[i].y = pa[i].y; }
-        const uint32_t nxt = idx + stride;
-        if (nxt < n_idx) fetch(nxt);
-        if (scale) {
-            const R sc = R(scale[0]);
-#pragma unroll
-            for (int i = 0; i < NR; ++i) { a[i].x *= sc; a[i].y *= sc; }
-        }
-        KOp op = op0;
-        for (uint32_t si = 0; si < ns; ++si) {
-            const StageHead h = stage_head(S0 + si);
-            uint32_t sl[NR];
-            reg_slots(h, thr_lds(h, t), sl);
-            if (si > 0) {
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    const C y = lds[sl[i]];
-                    a[i].x = y.x;
-                    a[i].y = y.y;
-                }
-            }
-            run_ops<R>(h, ops, coefs, a, op);
-            if (si + 1 == ns) break;
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                C y;
-                y.x = a[i].x;
-                y.y = a[i].y;
-                lds[sl[i]] = y;
-            }
-            lds_barrier();
-        }
-        // the next tile's loads were issued before this tile's stages
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-        C *dst = static_cast<C *>(dst_);
-        C *ck = static_cast<C *>(ckpt_);
-        uint64_t g[NR];
-        reg_goffs(SL, tile_base(idx) | gtl, g);
-        if (!store_mask) {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                C y;
-                y.x = a[i].x;
-                y.y = a[i].y;
-                dst[g[i]] = y;
-            }
-            if (ck) {
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    C y;
-                    y.x = a[i].x;
-                    y.y = a[i].y;
-                    ck[g[i]] = y;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                C y;
-                y.x = a[i].x;
-                y.y = a[i].y;
-                const uint64_t blk = g[i] >> block_bits;
-                if ((store_mask[blk >> 6] >> (blk & 63)) & 1) {
-                    dst[g[i]] = y;
-                    if (ck) ck[g[i]] = y;
-                }
-            }
-        }
-        if (partials) {
-            double acc = 0;
-#pragma unroll
-            for (int i = 0; i < NR; ++i) acc += double(a[i].x) * double(a[i].x) + double(a[i].y) * double(a[i].y);
-            __shared__ double red[16];
-            const double sum = block_sum(acc, red);
-            if (threadIdx.x == 0) partials[idx] = sum;
-        }
-        // the next tile reuses the LDS (and the reduction scratch)
-        if (nxt < n_idx && (ns > 1 || partials)) lds_barrier();
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(512)
-qk_pass_pf(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass,
-           const KStage *__restrict__ stages, const KOp *__restrict__ ops, const R *__restrict__ coefs,
-           const uint32_t *__restrict__ tile_list, uint32_t n_tiles, const uint64_t *__restrict__ store_mask,
-           const double *__restrict__ scale, double *__restrict__ partials, uint32_t src_basis,
-           uint32_t block_bits) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    using C = typename V2<R>::T;
-    pass_tiles_pf<R>(blockIdx.x, gridDim.x, n_tiles, tile_list, dst, src, ckpt, pass, stages, ops, coefs, store_mask,
-                     scale, partials, src_basis, block_bits, reinterpret_cast<C *>(smem));
-}
-
 // Pass kernel: one workgroup per tile.
 template <typename R, bool MF>
 __global__ void __launch_bounds__(512)
@@ -1102,52 +955,12 @@ hipError_t launch_pass_t(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s)
     return hipGetLastError();
 }
 
-// Workgroups of the persistent kernel: as many as are resident at once (by
-// registers and LDS), at most one per tile.
-uint32_t pf_grid(int b, size_t lds, uint32_t n_tiles) {
-    static int cache_dev = -1, cus = 0;
-    static int occ[QK_MAX_TILE_BITS + 1] = {0};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (dev != cache_dev) {
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-            (void)hipGetLastError();
-            cus = 1;
-        }
-        for (int &o : occ) o = 0;
-        cache_dev = dev;
-    }
-    if (occ[b] == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&qk_pass_pf<double>),
-                                                        int(1u << (b - QK_G)), lds) != hipSuccess || nb < 1) {
-            (void)hipGetLastError();
-            nb = 1;
-        }
-        occ[b] = nb;
-    }
-    const uint64_t g = uint64_t(occ[b]) * uint64_t(cus);
-    return uint32_t(g < n_tiles ? g : n_tiles);
-}
-
-hipError_t launch_pass_pf(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
-    const uint32_t threads = 1u << (b - QK_G);
-    const size_t lds = (size_t(1) << b) * sizeof(double2);
-    hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_pf<double>), lds);
-    if (e != hipSuccess) return e;
-    const uint32_t grid = pf_grid(b, lds, n_tiles);
-    hipLaunchKernelGGL(qk_pass_pf<double>, dim3(grid), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
-                       a.stages, a.ops, static_cast<const double *>(a.coefs), a.tile_list, n_tiles, a.store_mask,
-                       a.scale, a.partials, a.src_basis, a.block_bits);
-    return hipGetLastError();
-}
-
 hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
     (void)hipGetLastError();  // start from a clean error state
     if (n_tiles == 0) return hipSuccess;
     if (a.has_mfma)
         return dtype == 0 ? launch_pass_t<double, true>(a, n_tiles, b, s) : launch_pass_t<float, true>(a, n_tiles, b, s);
-    return dtype == 0 ? launch_pass_pf(a, n_tiles, b, s) : launch_pass_t<float, false>(a, n_tiles, b, s);
+    return dtype == 0 ? launch_pass_t<double, false>(a, n_tiles, b, s) : launch_pass_t<float, false>(a, n_tiles, b, s);
 }
 
 hipError_t launch_pass_batch(int dtype, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,

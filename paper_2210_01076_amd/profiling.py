@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--bench-json", required=True, help="output of the traced benchmark run")
     ap.add_argument("--counter-bench-json", required=True, help="output of the counter benchmark runs")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
-    ap.add_argument("--kernel", default="qk_pass_pf<double>")
+    ap.add_argument("--kernel", default="qk_pass<double, false>")
     ap.add_argument("--copy-kernel", default="qk_copy")
     ap.add_argument("--cmd-trace", default="")
     ap.add_argument("--cmd-fetch", default="")
