@@ -556,14 +556,9 @@ uint32_t lds_phys(uint32_t l, int swz) {
 }
 
 uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp) {
-    // 64-bit words through a splitmix finalizer (the plan cache is keyed by
-    // this value, so it mixes every bit of the kinds, qubits and matrices)
-    auto mix = [](uint64_t h, uint64_t w) {
-        uint64_t x = h + w * 0x9e3779b97f4a7c15ull;
-        x ^= x >> 30; x *= 0xbf58476d1ce4e5b9ull;
-        x ^= x >> 27; x *= 0x94d049bb133111ebull;
-        return x ^ (x >> 31);
-    };
+    // the plan cache is keyed by this value, so it mixes every bit of the
+    // kinds, qubits and matrices
+    auto mix = hash_mix;
     uint64_t h = 0x243f6a8885a308d3ull;
     const int64_t params[7] = {pp.n, pp.b, pp.c, pp.dtype, pp.fusion, pp.fuse_k, pp.swz};
     for (int64_t v : params) h = mix(h, uint64_t(v));

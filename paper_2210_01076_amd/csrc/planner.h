@@ -3,6 +3,7 @@
 // pass, into stages of register-resident work.
 #pragma once
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,26 @@ SegmentPlan plan_segment(const std::vector<LGate> &ops, const PlanParams &pp, ui
 
 // Hash of a segment's content and the parameters that shape its plan.
 uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp);
+
+// One 64-bit word into a running hash, through a splitmix finalizer.  Every
+// bit of the word reaches every bit of the result (an xor-multiply step
+// would not do: flipping the top bit of two words, as negating a complex
+// number does, cancels out in it).
+inline uint64_t hash_mix(uint64_t h, uint64_t w) {
+    uint64_t x = h + w * 0x9e3779b97f4a7c15ull;
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+// Bit pattern of a double, for hashing.
+inline uint64_t double_bits(double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, sizeof(b));
+    return b;
+}
 
 // LDS slot of tile index l under the swizzle of width `swz`.
 uint32_t lds_phys(uint32_t l, int swz);

@@ -137,6 +137,11 @@ std::vector<LGate> Session::level_ops(size_t lo, size_t hi) const {
 // Cut the circuit at its anchor levels.  The first time (no anchors) every
 // K-th level becomes an anchor; levels appended after the last anchor are cut
 // every K levels; a segment that grew to 2K levels through insertions is split.
+// The cut is a function of the circuit and the anchor set alone, and running
+// it again on what it returns changes nothing: an anchor on the last level
+// (which ends no segment) stays an anchor, since dropping it would move the
+// start of the tail and so the cuts of a second run.  An incremental update
+// and the full re-simulation that follows it then run the same segments.
 void Session::build_segments(const PlanParams &pp) {
     segs_.clear();
     const size_t D = circ.num_levels();
@@ -159,6 +164,8 @@ void Session::build_segments(const PlanParams &pp) {
             segs_.push_back(sg);
             used.insert(id);
             lo = i + 1;
+        } else if (anchors_.count(id)) {
+            used.insert(id);  // the last level
         }
     }
     if (D > 0) {
@@ -171,7 +178,7 @@ void Session::build_segments(const PlanParams &pp) {
     anchors_ = used;
     for (auto &sg : segs_) {
         uint64_t k = 1469598103934665603ull;
-        auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
+        auto mix = [&](uint64_t v) { k = hash_mix(k, v); };
         mix(uint64_t(pp.b) | uint64_t(pp.c) << 8 | uint64_t(pp.fusion) << 16 | uint64_t(pp.fuse_k) << 24 |
             uint64_t(pp.dtype) << 32);
         for (size_t i = sg.lo; i < sg.hi; ++i) {
@@ -250,10 +257,19 @@ bool same_pass(const PPass &a, const PPass &b) {
     return true;
 }
 
+// f(BlockAction) for every op of the pass in program order; a fused dense
+// stage is one op on all of its qubits
 template <typename F>
-void for_pass_ops(const PPass &p, F &&f) {
-    for (const auto &st : p.stages)
-        for (const auto &g : st.ops) f(g);
+void for_pass_actions(const PPass &p, int beta, F &&f) {
+    for (const auto &st : p.stages) {
+        if (!st.U.empty()) {
+            std::vector<int> qs;
+            for (int tb : st.tbits) qs.push_back(p.qlist[tb]);
+            f(dense_action(qs, beta));
+            continue;
+        }
+        for (const auto &g : st.ops) f(block_action(g, beta));
+    }
 }
 
 uint64_t pext_tile(uint64_t x, const uint8_t *pos, uint32_t npos) {
@@ -304,9 +320,9 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     // reach every block, the replay cannot be restricted.
     {
         auto gate_key = [](const LGate &g) {
-            uint64_t id = 1469598103934665603ull ^ g.kop;
-            for (int q = 0; q < g.nq; ++q) id = (id ^ uint64_t(g.q[q] + 1)) * 1099511628211ull;
-            return id ^ g.gate_id;
+            uint64_t id = hash_mix(1469598103934665603ull, g.kop);
+            for (int q = 0; q < g.nq; ++q) id = hash_mix(id, uint64_t(g.q[q] + 1));
+            return hash_mix(id, g.gate_id);
         };
         std::vector<std::pair<uint64_t, const LGate *>> a, b;
         for (const auto &p : op)
@@ -331,9 +347,9 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
         bool sat = lb.all();
         for (size_t s = s_edit; s < nseg && !sat; ++s)
             for (const auto &p : plans_[s]->passes) {
-                for_pass_ops(p, [&](const LGate &g) {
+                for_pass_actions(p, beta, [&](const BlockAction &ba) {
                     if (!sat) {
-                        propagate(block_action(g, beta), lb);
+                        propagate(ba, lb);
                         sat = lb.all();
                     }
                 });
@@ -352,26 +368,20 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     if (work * nblocks > (uint64_t(1) << 28)) return QTASK_E_UNSUPPORTED;
     auto seq_hash = [&](const std::vector<PPass> &passes) {
         std::vector<uint64_t> h(nblocks, 0);
-        auto mix = [&](uint64_t j, uint64_t v) { h[j] = (h[j] ^ v) * 0x100000001b3ull + 0x9e3779b97f4a7c15ull; };
+        auto mix = [&](uint64_t j, uint64_t v) { h[j] = hash_mix(h[j], v); };
         for (const auto &p : passes)
             for (const auto &stg : p.stages) {
                 if (!stg.U.empty()) {
                     uint64_t id = 1469598103934665603ull;
-                    for (const cd &z : stg.U) id = (id ^ std::hash<double>()(z.real()) ^ (std::hash<double>()(z.imag()) << 1)) * 1099511628211ull;
-                    for (int tb : stg.tbits) id = (id ^ uint64_t(p.qlist[tb])) * 1099511628211ull;
+                    for (const cd &z : stg.U) id = hash_mix(hash_mix(id, double_bits(z.real())), double_bits(z.imag()));
+                    for (int tb : stg.tbits) id = hash_mix(id, uint64_t(p.qlist[tb]));
                     for (uint64_t j = 0; j < nblocks; ++j) mix(j, id);
                     continue;
                 }
                 for (const auto &g : stg.ops) {
-                    uint64_t id = 1469598103934665603ull ^ g.kop;
-                    for (int q = 0; q < g.nq; ++q) id = (id ^ uint64_t(g.q[q] + 1)) * 1099511628211ull;
-                    for (const cd &z : g.m) {
-                        uint64_t re, im;
-                        std::memcpy(&re, &z, 8);
-                        std::memcpy(&im, reinterpret_cast<const char *>(&z) + 8, 8);
-                        id = (id ^ re) * 1099511628211ull;
-                        id = (id ^ im) * 1099511628211ull;
-                    }
+                    uint64_t id = hash_mix(1469598103934665603ull, g.kop);
+                    for (int q = 0; q < g.nq; ++q) id = hash_mix(id, uint64_t(g.q[q] + 1));
+                    for (const cd &z : g.m) id = hash_mix(hash_mix(id, double_bits(z.real())), double_bits(z.imag()));
                     for_rewritten_blocks(g, beta, nblocks, [&](uint64_t j) { mix(j, id); });
                 }
             }
@@ -384,7 +394,7 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     bool saturated = d.all();
     auto prop = [&](const PPass &p) {
         if (saturated) return;
-        for_pass_ops(p, [&](const LGate &g) { propagate(block_action(g, beta), d); });
+        for_pass_actions(p, beta, [&](const BlockAction &ba) { propagate(ba, d); });
         saturated = d.all();
     };
     for (size_t i = 0; i < np.size(); ++i) prop(np[i]);
@@ -395,8 +405,8 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     for (size_t s = s0; s < nseg; ++s)
         for (const auto &p : plans_[s]->passes) {
             bool ok = true;
-            for_pass_ops(p, [&](const LGate &g) {
-                if (ok && !closed_under(block_action(g, beta), d)) ok = false;
+            for_pass_actions(p, beta, [&](const BlockAction &ba) {
+                if (ok && !closed_under(ba, d)) ok = false;
             });
             if (!ok) return QTASK_E_UNSUPPORTED;
         }

@@ -1,6 +1,7 @@
 #include "tracker.h"
 
 #include <algorithm>
+#include <stdexcept>
 
 namespace qtask {
 
@@ -33,19 +34,26 @@ std::vector<uint32_t> BlockSet::list() const {
     return out;
 }
 
-BlockAction block_action(const LGate &g, int beta) {
+namespace {
+
+// Block structure of an op on the given qubits whose kernel reads entry
+// (r, c) of its matrix where reads(r, c) holds (local bit of qubit j is
+// k-1-j).
+template <typename Reads>
+BlockAction make_action(const int *q, int k, int beta, Reads &&reads) {
     BlockAction a;
-    const int k = g.nq, dim = 1 << k;
-    // local bit of gate qubit j is (k-1-j); split local index into high part
-    // (qubits >= beta, in hmask order) and low part
-    std::vector<int> hi_j;  // gate qubit indices j with q >= beta, ascending by qubit
+    const int dim = 1 << k;
+    // split the local index into its high part (qubits >= beta, ascending
+    // by qubit) and the rest
+    std::vector<int> hi_j;  // gate qubit indices j with q >= beta
     for (int j = 0; j < k; ++j)
-        if (g.q[j] >= beta) hi_j.push_back(j);
-    std::sort(hi_j.begin(), hi_j.end(), [&](int x, int y) { return g.q[x] < g.q[y]; });
+        if (q[j] >= beta) hi_j.push_back(j);
+    std::sort(hi_j.begin(), hi_j.end(), [&](int x, int y) { return q[x] < q[y]; });
     a.nh = int(hi_j.size());
+    if (a.nh > QK_MAX_DENSE_K) throw std::logic_error("op on too many block qubits");
     for (int j : hi_j) {
-        a.hmask |= uint64_t(1) << (g.q[j] - beta);
-        a.hq.push_back(g.q[j] - beta);
+        a.hmask |= uint64_t(1) << (q[j] - beta);
+        a.hq.push_back(q[j] - beta);
     }
     const int hd = 1 << a.nh;
     auto hpart = [&](int local) {
@@ -53,24 +61,33 @@ BlockAction block_action(const LGate &g, int beta) {
         for (int i = 0; i < a.nh; ++i) h |= ((local >> (k - 1 - hi_j[i])) & 1) << i;
         return h;
     };
-    a.touched.assign(hd, 0);
     a.couple.assign(size_t(hd) * hd, 0);
-    for (int r = 0; r < dim; ++r) {
-        bool identity_row = true;
-        for (int c = 0; c < dim; ++c) {
-            const cd v = g.m[size_t(r) * dim + c];
-            if (v != (r == c ? cd(1, 0) : cd(0, 0))) identity_row = false;
-            if (v != cd(0, 0) && hpart(r) != hpart(c)) {
+    for (int r = 0; r < dim; ++r)
+        for (int c = 0; c < dim; ++c)
+            if (hpart(r) != hpart(c) && reads(r, c)) {
                 a.couple[size_t(hpart(r)) * hd + hpart(c)] = 1;
                 a.any_couple = true;
             }
-        }
-        if (!identity_row) {
-            a.touched[hpart(r)] = 1;
-            a.any_touch = true;
-        }
-    }
     return a;
+}
+
+}  // namespace
+
+BlockAction block_action(const LGate &g, int beta) {
+    const int k = g.nq, dim = 1 << k;
+    switch (g.kop) {
+    case KOP_D1: case KOP_P1: case KOP_P2: case KOP_GPH:
+        return make_action(g.q, k, beta, [](int, int) { return false; });
+    case KOP_X1: case KOP_CX: case KOP_SWAP: case KOP_CCX:
+        // exact exchanges: the matrix is the permutation the kernel moves by
+        return make_action(g.q, k, beta, [&](int r, int c) { return g.m[size_t(r) * dim + c] != cd(0, 0); });
+    default:  // dense forms: every entry of a row is read
+        return make_action(g.q, k, beta, [](int, int) { return true; });
+    }
+}
+
+BlockAction dense_action(const std::vector<int> &qubits, int beta) {
+    return make_action(qubits.data(), int(qubits.size()), beta, [](int, int) { return true; });
 }
 
 void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std::function<void(uint64_t)> &f) {
@@ -117,7 +134,7 @@ namespace {
 template <typename F>
 void for_groups(const BlockAction &a, uint64_t nblocks, F &&f) {
     const int hd = 1 << a.nh;
-    uint64_t idx[8];
+    uint64_t idx[1 << QK_MAX_DENSE_K];
     for (uint64_t base = 0; base < nblocks; ++base) {
         if (base & a.hmask) continue;
         for (int h = 0; h < hd; ++h) {
@@ -131,21 +148,11 @@ void for_groups(const BlockAction &a, uint64_t nblocks, F &&f) {
 }
 }  // namespace
 
-void add_touched(const BlockAction &a, BlockSet &out) {
-    if (!a.any_touch) return;
-    const int hd = 1 << a.nh;
-    for_groups(a, out.size(), [&](const uint64_t *idx) {
-        for (int h = 0; h < hd; ++h)
-            if (a.touched[h]) out.set(idx[h]);
-        return true;
-    });
-}
-
 void propagate(const BlockAction &a, BlockSet &d) {
     if (!a.any_couple) return;
     const int hd = 1 << a.nh;
     for_groups(a, d.size(), [&](const uint64_t *idx) {
-        bool in[8];
+        bool in[1 << QK_MAX_DENSE_K];
         for (int h = 0; h < hd; ++h) in[h] = d.test(idx[h]);
         for (int ho = 0; ho < hd; ++ho)
             for (int hi = 0; hi < hd; ++hi)

@@ -37,18 +37,26 @@ private:
     std::vector<uint64_t> w_;
 };
 
-// Per-gate block structure, precomputed from the gate's matrix.
+// Which blocks an op reads from which, as the kernel runs it.  The coupling
+// follows the op's kernel form, not its matrix values: a dense 2x2 (or a fused
+// dense stage) reads every amplitude of its group even where its matrix has
+// an exact zero, and the product 0 * x still decides the sign of a zero
+// result, so a block it pairs with a stale partner could come out with
+// different bits.  Diagonal ops read nothing across blocks; exchanges read
+// exactly the partner they move.
 struct BlockAction {
     uint64_t hmask = 0;            // block-index bits of the gate's qubits >= beta
-    int nh = 0;                    // number of such qubits
-    std::vector<uint8_t> touched;  // touched[h]: some amplitude with high part h can change
+    int nh = 0;                    // number of such qubits (at most QK_MAX_DENSE_K)
     std::vector<uint8_t> couple;   // couple[h_out * 2^nh + h_in]: h_out != h_in mix
     bool any_couple = false;
-    bool any_touch = false;
     std::vector<int> hq;           // block-index bit of high qubit i (i-th in hmask order)
 };
 
 BlockAction block_action(const LGate &g, int beta);
+
+// A fused dense stage on the given qubits: every amplitude of a group reads
+// every other one.
+BlockAction dense_action(const std::vector<int> &qubits, int beta);
 
 // Blocks whose amplitudes the kernel rewrites when it runs this op (decided
 // by the op's kernel form, not by matrix values): controlled and phase ops
@@ -56,8 +64,6 @@ BlockAction block_action(const LGate &g, int beta);
 // op rewrites its whole support.  Calls f(block) for each such block.
 void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std::function<void(uint64_t)> &f);
 
-// out |= blocks the gate can change
-void add_touched(const BlockAction &a, BlockSet &out);
 // d |= blocks coupled to d by the gate
 void propagate(const BlockAction &a, BlockSet &d);
 // true when the gate couples no block of s with a block outside s

@@ -2,6 +2,7 @@
 modified circuit, and bitwise equal to a full GPU re-simulation."""
 import json
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -188,3 +189,75 @@ def test_layered_24_full_size_against_oracle():
             e64 = float(np.max(np.abs(a - b)))
             log("layered-24 complex64 vs complex128: max-abs %.2e, fidelity 1 - %.1e" % (e64, 1 - f))
             assert e64 <= 1e-5 and f >= 1 - 1e-6
+
+
+def _edit_family(family, n, seed):
+    if family == "dense":
+        return W.dense_random_circuit(n, 16, 901 + seed, kinds=W.GATE_KINDS), ("h", "x", "cx", "cz", "rz", "swap", "t")
+    if family == "layered":
+        return W.layered_circuit(n, 10, 902 + seed), W.LAYERED_EDIT_KINDS
+    if family == "ladder":
+        return W.cp_ladder_circuit(n, 8, 903 + seed), ("rx", "rz", "cp")
+    # permutations and phases only: the restricted replay applies often
+    return (W.dense_random_circuit(n, 16, 904 + seed, kinds=("x", "cx", "ccx", "swap", "z", "s", "t", "cz", "cp")),
+            ("x", "cx", "z", "cz", "t", "swap"))
+
+
+def _edit_sequence(n, nets, kinds, dtype, K, rng, steps):
+    """Random gate and level inserts and removals; after every update the
+    state must equal a full re-simulation bit for bit."""
+    modes = []
+    with sim(n, nets, dtype, ckpt_interval=K, block_bits=4, tile_bits=8, low_bits=3) as s:
+        s.update()
+        for step in range(steps):
+            r = rng.random()
+            if r < 0.15 and len(nets) > 2:
+                li = int(rng.integers(len(nets)))
+                del nets[li]
+                s.remove_level(li)
+                what = "remove level %d" % li
+            elif r < 0.3:
+                li = int(rng.integers(len(nets) + 1))
+                kind = kinds[int(rng.integers(len(kinds)))]
+                qs = tuple(int(q) for q in rng.choice(n, size=W.N_QUBITS[kind], replace=False))
+                g = (kind, qs, tuple(float(x) for x in rng.uniform(0, 6, W.N_PARAMS[kind])))
+                nets.insert(li, [g])
+                s.add_level(li)
+                s.add_gate(li, g)
+                what = "insert level %d %s" % (li, g)
+            else:
+                e = W.random_edit(rng, n, nets, kinds)
+                W.apply_edit(nets, e)
+                s.apply_edit(e)
+                what = str(e)
+            st = s.update()
+            modes.append(st["mode"])
+            inc = s.state()
+            s.update(full=True)
+            assert bytes_equal(inc, s.state()), "step %d (%s): mode %d from level %d, %d dirty blocks" % (
+                step, what, st["mode"], st["first_level"], st["dirty_blocks"])
+        check_state(s.state(), oracle.simulate(n, nets), dtype, "after the edits")
+    return modes
+
+
+@pytest.mark.parametrize("family,dtype,K", [("dense", "c128", 3), ("layered", "c64", 4), ("ladder", "c128", 5),
+                                            ("arith", "c128", 2)])
+def test_random_edit_sequences_stay_bitwise_equal(family, dtype, K):
+    """Long random sequences of gate and level inserts and removals, with the
+    restricted replay enabled: after every update the state equals a full
+    re-simulation bit for bit, and at the end it matches the oracle."""
+    rng = np.random.default_rng(zlib.crc32(("%s/%s/%d" % (family, dtype, K)).encode()))
+    nets, kinds = _edit_family(family, 12, 0)
+    modes = _edit_sequence(12, nets, kinds, dtype, K, rng, 60)
+    log(family, dtype, "modes", {m: modes.count(m) for m in set(modes)})
+
+
+@pytest.mark.parametrize("seed", [28, 40, 78, 88, 209, 224, 293])
+def test_edit_sequences_with_level_removals_and_merged_phases(seed):
+    """Sequences that once broke bitwise equality: a level removal that left
+    an anchor on the last level (the full re-simulation after it cut the
+    segments differently), and a removed Z that negated a merged phase (the
+    restricted replay saw no changed block)."""
+    family = ("dense", "ladder", "arith")[seed % 3]
+    nets, kinds = _edit_family(family, 12, seed)
+    _edit_sequence(12, nets, kinds, "c128", 2 + seed % 4, np.random.default_rng(seed), 25)

@@ -370,6 +370,102 @@ def test_level_removal_inside_a_segment_stays_closed():
         assert changed and changed <= dirty and len(dirty) < 1 << (n - bb)
 
 
+def test_tracker_sees_a_merged_phase_change_sign():
+    """Removing a Z from a qubit that also carries a T turns their merged phase
+    e^{i pi/4} * -1 into e^{i pi/4}: real and imaginary parts both change
+    sign.  The per-block identities must tell the two plans apart (a hash
+    whose step is xor-then-multiply does not: the two top-bit flips cancel),
+    so the restricted replay covers the blocks that change."""
+    n, bb = 7, 3
+    nets = [[("h", (q,), ()) for q in range(n)]]
+    nets += [[("cx", (6, 5), ())], [("s", (3,), ())], [("cz", (0, 4), ())], [("t", (6,), ())],
+             [("z", (6,), ())], [("t", (5,), ())], [("z", (2,), ())], [("s", (5,), ())]]
+    with plan_only(n, block_bits=bb, ckpt_interval=4, tile_bits=5, low_bits=2) as sim:
+        sim.build(nets)
+        sim.update()
+        old = [list(x) for x in nets]
+        del nets[5]
+        sim.remove_level(5)
+        st = sim.update()
+        assert st["mode"] == 3
+        dirty = set(sim.dump()["dirty_block_list"])
+        changed = oracle.changed_blocks(oracle.snapshots(n, old)[-1], oracle.snapshots(n, nets)[-1], bb)
+        assert changed and changed <= dirty
+
+
+def test_tracker_couples_blocks_through_a_fused_near_identity():
+    """Two H on a block qubit fuse into one real 2x2 whose off-diagonal
+    entries are exactly zero.  The kernel still reads the partner amplitude
+    (0 * x decides the sign of a zero result), so a restricted replay must not
+    pair a recomputed block with a partner it leaves stale: after the CZ on
+    that qubit is removed, either the replay is not restricted or its block
+    set is closed under the pairing and covers what changed."""
+    n, bb = 7, 3
+    nets = [[("h", (q,), ()) for q in range(n)]]
+    nets += [[("cx", (5, 4), ())], [("s", (3,), ())], [("cz", (0, 4), ())], [("h", (6,), ())],
+             [("h", (6,), ())], [("cz", (6, 1), ())], [("t", (2,), ())], [("s", (5,), ())]]
+    with plan_only(n, block_bits=bb, ckpt_interval=4, tile_bits=5, low_bits=2) as sim:
+        sim.build(nets)
+        sim.update()
+        ops = [(o["kop"], o["gate"], o["q"]) for seg in sim.dump()["segments"] for p in seg["passes"]
+               for st in p["stages"] for o in st["ops"]]
+        assert (12, 0, [6]) in ops  # the fused H.H
+        old = [list(x) for x in nets]
+        del nets[6]
+        sim.remove_level(6)
+        st = sim.update()
+        if st["mode"] == 3:
+            dirty = set(sim.dump()["dirty_block_list"])
+            pair = 1 << (6 - bb)
+            assert all(j ^ pair in dirty for j in dirty)
+            changed = oracle.changed_blocks(oracle.snapshots(n, old)[-1], oracle.snapshots(n, nets)[-1], bb)
+            assert changed <= dirty
+
+
+def test_segments_survive_a_full_rerun_after_level_removal():
+    """The segment cut depends on the circuit and the anchor set only and is
+    stable under a second run: after levels are inserted and the last one is
+    removed (leaving an anchor on the new last level), the incremental update
+    and the full re-simulation after it plan the same segments, which is what
+    keeps their results bitwise equal."""
+    n = 6
+    nets = [[("h", (q % n,), ())] for q in range(7)]
+    with plan_only(n, ckpt_interval=2, tile_bits=5, low_bits=2) as sim:
+        sim.build(nets)
+        sim.update()
+        g = ("rz", (1,), (0.3,))
+        nets.insert(5, [g])
+        sim.add_level(5)
+        sim.add_gate(5, g)
+        sim.update()
+        del nets[7]
+        sim.remove_level(7)
+        sim.update()
+        inc = json.dumps(sim.dump()["segments"])
+        sim.update(full=True)
+        assert json.dumps(sim.dump()["segments"]) == inc
+    # random edit sequences with level removals
+    for seed in (28, 40, 209, 224):
+        rng = np.random.default_rng(seed)
+        nets = W.cp_ladder_circuit(8, 6, 903 + seed)
+        with plan_only(8, ckpt_interval=2 + seed % 3, tile_bits=6, low_bits=3) as sim:
+            sim.build(nets)
+            sim.update()
+            for _ in range(20):
+                if rng.random() < 0.3 and len(nets) > 2:
+                    li = int(rng.integers(len(nets)))
+                    del nets[li]
+                    sim.remove_level(li)
+                else:
+                    e = W.random_edit(rng, 8, nets, ("rx", "rz", "cp"))
+                    W.apply_edit(nets, e)
+                    sim.apply_edit(e)
+                sim.update()
+                inc = json.dumps(sim.dump()["segments"])
+                sim.update(full=True)
+                assert json.dumps(sim.dump()["segments"]) == inc
+
+
 def test_server_opts_and_edit_records():
     o = Q.qtask_server_opts_default()
     assert o.struct_size == Q.ctypes.sizeof(Q.qtask_server_opts)
