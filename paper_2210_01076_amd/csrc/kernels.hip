@@ -598,8 +598,9 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
             lds_barrier();
             continue;
         }
+        uint32_t bt = thr_lds(h, t);
         uint32_t sl[NR];
-        reg_slots(h, thr_lds(h, t), sl);
+        reg_slots(h, bt, sl);
         if (si == 0) {
             uint64_t g[NR];
             reg_goffs(S, base | thr_glb(S, t), g);
@@ -633,6 +634,12 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
         }
         run_ops<R>(h, ops, coefs, a, op);
         if (si + 1 == ns) break;
+        // complex128: recompute the slots instead of keeping them live across
+        // the op loop (16 fewer registers; see the kernel's occupancy hint)
+        if constexpr (sizeof(R) == 8) {
+            asm volatile("" : "+v"(bt));
+            reg_slots(h, bt, sl);
+        }
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             C y;
@@ -700,6 +707,22 @@ qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, 
     using C = typename V2<R>::T;
     pass_tile<R, MF>(blockIdx.x, tile_list, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale, partials,
                      src_basis, block_bits, reinterpret_cast<C *>(smem));
+}
+
+// The complex128 vector-ALU kernel asks for at least three waves per SIMD:
+// its body then fits 168 registers without spilling (two waves otherwise).
+// The matrix-core variants would spill under the same limit and keep the
+// default.
+template <>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+qk_pass<double, false>(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass,
+                       const KStage *__restrict__ stages, const KOp *__restrict__ ops,
+                       const double *__restrict__ coefs, const uint32_t *__restrict__ tile_list,
+                       const uint64_t *__restrict__ store_mask, const double *__restrict__ scale,
+                       double *__restrict__ partials, uint32_t src_basis, uint32_t block_bits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass_tile<double, false>(blockIdx.x, tile_list, dst, src, ckpt, pass, stages, ops, coefs, store_mask, scale,
+                             partials, src_basis, block_bits, reinterpret_cast<V2<double>::T *>(smem));
 }
 
 // Batched pass round over many small sessions that share one tile shape.
