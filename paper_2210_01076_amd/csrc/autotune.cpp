@@ -6,10 +6,10 @@
 // instead: at the first update of a session it plans the circuit's first
 // levels with every candidate, runs each plan on the device (twice, keeping
 // the second timing, unless the first is already well behind), and keeps the
-// fastest.  The pick is cached per (device, state qubits, dtype, requested
-// fusion mode and width, gate mix) and frozen for the session, so every later
-// plan of the session, full or incremental, uses the same shape and results
-// stay bitwise reproducible.
+// fastest (near-ties go to the smaller tile).  The pick is cached per
+// (device, state qubits, dtype, requested fusion mode and width, gate mix)
+// and frozen for the session, so every later plan of the session, full or
+// incremental, uses the same shape and results stay bitwise reproducible.
 #include <array>
 #include <map>
 #include <mutex>
@@ -130,7 +130,12 @@ int Session::autotune() {
             last_error = "autotune: device error";
             return rc;
         }
-        if (ms < best_t) {
+        // a later candidate (larger tile, then more fixed low bits) must be
+        // clearly faster: within 1% -- about the spread of two timings of the
+        // same plan -- the smaller tile is kept, since a restricted
+        // incremental replay recomputes whole tiles and so redoes less work
+        // with smaller ones
+        if (ms < 0.99 * best_t) {
             best_t = ms;
             best = bc;
         }
