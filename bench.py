@@ -49,9 +49,13 @@ def fidelity(a, b):
     return float(abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
 
 
-def run_tier(Q, W, wl, dtype, steps, warmup):
+def run_tier(Q, W, wl, dtype, steps, warmup, shape=None):
     nets = [list(x) for x in wl.nets]
-    sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=1)
+    if shape:  # a pinned tile shape (b, c) instead of the autotuner's pick
+        sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=0,
+                          tile_bits=shape[0], low_bits=shape[1])
+    else:
+        sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=1)
     sim.build(nets)
     t0 = time.perf_counter()
     st = sim.update()          # first update: autotune + full simulation
@@ -506,6 +510,10 @@ def main():
     ap.add_argument("--no-fused-tuned", action="store_true",
                     help="skip the autotuned comparison run of the fused-unitary leg (its timing candidates "
                          "would mix into a profile of the fused kernels)")
+    ap.add_argument("--tile-bits", type=int, default=0,
+                    help="pin the complex128 tier's tile bits instead of autotuning (profiling runs: counter "
+                         "collection slows kernels and would sway the tuner's timings)")
+    ap.add_argument("--low-bits", type=int, default=3, help="contiguous low bits with --tile-bits")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -533,7 +541,8 @@ def main():
     copy_gbs = Q.qtask_copy_bandwidth(0, 1 << 30, 20)
     log("copy kernel ceiling %.1f GB/s" % copy_gbs)
     wl = W.config(2)
-    sim128, nets, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup)
+    shape = (args.tile_bits, args.low_bits) if args.tile_bits else None
+    sim128, nets, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup, shape)
     r64 = None
     if not args.no_c64:
         sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup)
@@ -544,6 +553,15 @@ def main():
         r64["fidelity_vs_c128"] = fidelity(a, b)
         sim64.close()
     sim128.close()
+
+    # before the serving leg: autotuner picks are cached per (qubits, dtype,
+    # gate mix), and the serving sessions tune while other sessions run, so
+    # a 28-qubit pick made there would be timed under contention
+    large = None
+    if not args.no_large:
+        large = run_large(Q, W)
+        log("28-qubit complex128 full simulation: %.1f ms, %.0f GB/s (%.2f of peak)" % (
+            large["full_ms"], large["gbs"], large["frac_of_peak"]))
 
     serving = None
     if not args.no_serving:
@@ -574,12 +592,6 @@ def main():
             log("%s: %d steps, update p50 %.2f ms p99 %.2f ms, speedup vs full p50 %s, mismatches %d" % (
                 k, p["steps"], p["update_ms_p50"], p["update_ms_p99"],
                 "%.1f" % p["speedup_p50"] if p["speedup_p50"] else "-", p["mismatches"]))
-    large = None
-    if not args.no_large:
-        large = run_large(Q, W)
-        log("28-qubit complex128 full simulation: %.1f ms, %.0f GB/s (%.2f of peak)" % (
-            large["full_ms"], large["gbs"], large["frac_of_peak"]))
-
     fused = None
     if not args.no_fused:
         fused = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels, tuned=not args.no_fused_tuned)

@@ -5,11 +5,13 @@
 // on the circuit and the machine (Section IV-F).  Here the library measures
 // instead: at the first update of a session it plans the circuit's first
 // levels with every candidate, runs each plan on the device (twice, keeping
-// the second timing, unless the first is already well behind), and keeps the
-// fastest (near-ties go to the smaller tile).  The pick is cached per
+// the second timing, unless the first is already well behind), times the
+// three fastest again on the whole first segment, and keeps the fastest of
+// those (near-ties go to the smaller tile).  The pick is cached per
 // (device, state qubits, dtype, requested fusion mode and width, gate mix)
 // and frozen for the session, so every later plan of the session, full or
 // incremental, uses the same shape and results stay bitwise reproducible.
+#include <algorithm>
 #include <array>
 #include <map>
 #include <mutex>
@@ -38,16 +40,18 @@ int Session::autotune() {
     if (plan_only) return QTASK_OK;
     int rc = init_device();
     if (rc != QTASK_OK) return rc;
-    // tuning prefix: the first levels, at most one segment, at most ~600 gates
-    std::vector<LGate> ops;
+    // the circuit's first segment (at most ~3000 gates) and its prefix of at
+    // most ~600 gates
+    std::vector<LGate> seg, ops;
     {
         const size_t D = circ.num_levels();
-        for (size_t li = 0; li < D && li < size_t(K()) && ops.size() < 600; ++li) {
+        for (size_t li = 0; li < D && li < size_t(K()) && seg.size() < 3000; ++li) {
             const Level &lv = circ.level_by_index(li);
             for (uint64_t gid : lv.gates) {
                 const Gate &g = circ.gate(gid);
-                ops.push_back(lower_gate(g.kind, g.q, g.p, g.id));
+                seg.push_back(lower_gate(g.kind, g.q, g.p, g.id));
             }
+            if (ops.size() < 600) ops = seg;  // the prefix ends with the level that reaches 600
         }
     }
     if (ops.empty()) return QTASK_OK;
@@ -82,9 +86,12 @@ int Session::autotune() {
                 if (b <= n_int && b - k >= 4) cand.push_back({b, 4, QTASK_FUSE_DENSE, k});
     if (cand.empty())
         cand.push_back({std::min(opts.tile_bits, n_int), std::min(opts.low_bits, n_int), opts.fusion, opts.fuse_width});
-    double best_t = 1e300;
-    Cand best = cand.front();
-    for (const auto &bc : cand) {
+
+    // Device time of one candidate's plan of `gates`, run `reps` times (the
+    // last run counts; a run slower than `cutoff` ms ends the repetitions).
+    // A candidate the planner rejects gets +inf.
+    auto time_plan = [&](const std::vector<LGate> &gates, const Cand &bc, int reps, double cutoff, double &out) {
+        out = 1e300;
         PlanParams pp;
         pp.n = n_int;
         pp.b = bc.b;
@@ -95,19 +102,18 @@ int Session::autotune() {
         pp.swz = dtype == QTASK_C128 ? 4 : 5;
         SegmentPlan sp;
         try {
-            sp = plan_segment(ops, pp);
+            sp = plan_segment(gates, pp);
         } catch (const std::exception &e) {
-            continue;
+            return QTASK_OK;
         }
-        rc = upload_plan(sp);
-        if (rc != QTASK_OK) return rc;
+        int r = upload_plan(sp);
+        if (r != QTASK_OK) return r;
         float ms = 0;
-        for (int rep = 0; rep < 2 && rc == QTASK_OK; ++rep) {
-            // a first run well behind the best so far cannot win: skip the second
-            if (rep == 1 && ms > 1.3 * best_t) break;
-            if (hipEventRecord(ev0_, stream) != hipSuccess) rc = QTASK_E_DEVICE;
+        for (int rep = 0; rep < reps && r == QTASK_OK; ++rep) {
+            if (rep > 0 && ms > cutoff) break;
+            if (hipEventRecord(ev0_, stream) != hipSuccess) r = QTASK_E_DEVICE;
             const char *blob = static_cast<const char *>(sp.dev);
-            for (size_t p = 0; p < sp.passes.size() && rc == QTASK_OK; ++p) {
+            for (size_t p = 0; p < sp.passes.size() && r == QTASK_OK; ++p) {
                 KArgs a{};
                 a.dst = state_.p;
                 a.src = p == 0 ? nullptr : state_.p;
@@ -118,28 +124,60 @@ int Session::autotune() {
                 a.coefs = blob + sp.off_coef;
                 a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
                 if (launch_pass(dtype, a, uint32_t(uint64_t(1) << (n_int - pp.b)), pp.b, stream) != hipSuccess)
-                    rc = QTASK_E_DEVICE;
+                    r = QTASK_E_DEVICE;
             }
-            if (rc == QTASK_OK && (hipEventRecord(ev1_, stream) != hipSuccess ||
-                                   hipStreamSynchronize(stream) != hipSuccess ||
-                                   hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
-                rc = QTASK_E_DEVICE;
+            if (r == QTASK_OK && (hipEventRecord(ev1_, stream) != hipSuccess ||
+                                  hipStreamSynchronize(stream) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
+                r = QTASK_E_DEVICE;
         }
         dfree(sp.dev);
-        if (rc != QTASK_OK) {
-            last_error = "autotune: device error";
-            return rc;
-        }
-        // a later candidate (larger tile, then more fixed low bits) must be
-        // clearly faster: within 1% -- about the spread of two timings of the
-        // same plan -- the smaller tile is kept, since a restricted
-        // incremental replay recomputes whole tiles and so redoes less work
-        // with smaller ones
-        if (ms < 0.99 * best_t) {
-            best_t = ms;
-            best = bc;
-        }
+        if (r == QTASK_OK) out = ms;
+        return r;
+    };
+
+    // Round 1: every candidate on the prefix, twice (a first run well behind
+    // the best so far cannot win and skips the second).
+    std::vector<double> t1(cand.size(), 1e300);
+    double best1 = 1e300;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        rc = time_plan(ops, cand[i], 2, 1.3 * best1, t1[i]);
+        if (rc != QTASK_OK) break;
+        best1 = std::min(best1, t1[i]);
     }
+    // Round 2: the three fastest on the whole first segment.  The prefix ends
+    // in a partly filled pass whose share differs between shapes by up to one
+    // pass in twenty; over the segment that error is a few times smaller.
+    std::vector<size_t> order(cand.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return t1[x] < t1[y]; });
+    std::vector<size_t> finalists;
+    for (size_t i : order)
+        if (finalists.size() < 3 && t1[i] < 1e300) finalists.push_back(i);
+    std::sort(finalists.begin(), finalists.end());  // back to candidate order
+    std::vector<double> t2(cand.size(), 1e300);
+    if (rc == QTASK_OK && seg.size() > ops.size() && finalists.size() > 1)
+        for (size_t i : finalists) {
+            rc = time_plan(seg, cand[i], 1, 0, t2[i]);
+            if (rc != QTASK_OK) break;
+        }
+    if (rc != QTASK_OK) {
+        last_error = "autotune: device error";
+        return rc;
+    }
+    const std::vector<double> &score = seg.size() > ops.size() && finalists.size() > 1 ? t2 : t1;
+    // A later candidate (larger tile, then more fixed low bits) must be
+    // clearly faster: within 1% -- about the spread of two timings of one
+    // plan -- the earlier one is kept.  The pick is then the same from run to
+    // run where shapes tie, and a restricted incremental replay, which
+    // recomputes whole tiles, redoes less work with the smaller tile.
+    Cand best = cand.front();
+    double best_t = 1e300;
+    for (size_t i : finalists.empty() ? std::vector<size_t>{0} : finalists)
+        if (score[i] < 0.99 * best_t) {
+            best_t = score[i];
+            best = cand[i];
+        }
     opts.tile_bits = best.b;
     opts.low_bits = best.c;
     opts.fusion = best.fusion;
