@@ -261,3 +261,41 @@ def test_edit_sequences_with_level_removals_and_merged_phases(seed):
     family = ("dense", "ladder", "arith")[seed % 3]
     nets, kinds = _edit_family(family, 12, seed)
     _edit_sequence(12, nets, kinds, "c128", 2 + seed % 4, np.random.default_rng(seed), 25)
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_random_shapes_and_dtypes_stay_bitwise_equal(block):
+    """Random edit sequences over random session shapes: 8-14 qubits, tile
+    bits 4-10, low bits, tracker block bits 1-6, checkpoint intervals 1-6,
+    both dtypes and four circuit families.  After every update the state
+    equals a full re-simulation bit for bit; at the end it matches the
+    oracle."""
+    for seed in range(block * 10, block * 10 + 10):
+        rng = np.random.default_rng(100000 + seed)
+        n = int(rng.integers(8, 15))
+        family = ("dense", "ladder", "arith", "layered")[seed % 4]
+        dtype = "c64" if seed % 5 == 0 else "c128"
+        K = int(rng.integers(1, 7))
+        b = int(rng.integers(4, min(n, 10) + 1))
+        c = int(rng.integers(1, b - 3 + 1)) if b > 4 else 1
+        bb = int(rng.integers(1, min(n, 6) + 1))
+        nets, kinds = _edit_family(family, n, seed)
+        if family == "dense":
+            kinds = ("h", "x", "y", "cx", "cz", "rz", "rx", "swap", "t", "sdg", "ccx", "ry", "cp")
+        log("seed %d: %s %s n=%d K=%d b=%d c=%d block_bits=%d" % (seed, family, dtype, n, K, b, c, bb))
+        with sim(n, nets, dtype, ckpt_interval=K, block_bits=bb, tile_bits=b, low_bits=c) as s:
+            s.update()
+            for step in range(15):
+                if rng.random() < 0.15 and len(nets) > 2:
+                    li = int(rng.integers(len(nets)))
+                    del nets[li]
+                    s.remove_level(li)
+                else:
+                    e = W.random_edit(rng, n, nets, kinds)
+                    W.apply_edit(nets, e)
+                    s.apply_edit(e)
+                st = s.update()
+                inc = s.state()
+                s.update(full=True)
+                assert bytes_equal(inc, s.state()), "seed %d step %d mode %d" % (seed, step, st["mode"])
+            check_state(s.state(), oracle.simulate(n, nets), dtype, "seed %d" % seed)
