@@ -651,7 +651,9 @@ def main():
                      "kernel": "qk_pass<double, false>", "bytes_per_launch": r128["launch_bytes"],
                      "avg_launch_ms": r128["launch_ms"], "launches_timed": r128["launches"],
                      "block": 1 << (r128["tile_bits"] - 4),
-                     "scope": "every pass launch of the timed steps (incremental and full), complex128"},
+                     "scope": "every pass launch of the timed steps (incremental and full), complex128",
+                     "note": "cache-assisted: the 24-qubit complex128 state (256 MiB) is about the size of the "
+                             "256 MB Infinity Cache; large_state is the HBM-only figure (28 qubits, 4 GiB)"},
         "append_protocol": append,
         "other_protocols": protocols,
         "large_state": large,

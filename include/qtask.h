@@ -205,7 +205,10 @@ int qtask_device_bytes(qtask_t h, uint64_t *out);
 /* The options in effect (after defaults and autotuning). */
 int qtask_get_opts(qtask_t h, qtask_opts *out);
 /* Write the current plan (passes, stages, ops, fused unitaries, affected
- * blocks of the last update) as JSON to `path`.  Paper: dump_graph (Table II). */
+ * blocks of the last update) as JSON to `path`.  A path ending in ".dot"
+ * gets the pass graph in Graphviz DOT instead: one cluster per segment, one
+ * node per pass in execution order, checkpoint boundaries marked.  Paper:
+ * dump_graph (Table II).  QTASK_E_ARG if the file cannot be written. */
 int qtask_dump_plan(qtask_t h, const char *path);
 
 /* ----------------------------------------------------------- diagnostics */

@@ -880,7 +880,56 @@ int Session::hash(uint64_t *out) {
     return QTASK_OK;
 }
 
+// Graphviz form of the plan: one cluster per segment (its level range), one
+// node per pass in execution order (its tile qubits and, per stage, the
+// register qubits and op count), edges in execution order; an edge that
+// crosses a segment boundary says whether a checkpoint is stored there.
+std::string Session::plan_dot() const {
+    std::ostringstream o;
+    o << "digraph qtask {\n  rankdir=LR;\n  node [shape=box, fontname=\"monospace\"];\n";
+    std::vector<std::string> nodes;
+    std::vector<size_t> seg_of;
+    const size_t S = std::min(segs_.size(), plans_.size());
+    for (size_t s = 0; s < S; ++s) {
+        o << "  subgraph cluster_s" << s << " {\n    label=\"segment " << s << ": levels [" << segs_[s].lo << ", "
+          << segs_[s].hi << ")\";\n";
+        const auto &passes = plans_[s]->passes;
+        for (size_t p = 0; p < passes.size(); ++p) {
+            const std::string id = "p" + std::to_string(s) + "_" + std::to_string(p);
+            o << "    " << id << " [label=\"pass " << p << "\\lqubits";
+            for (int q : passes[p].qlist) o << " " << q;
+            o << "\\l";
+            for (const auto &st : passes[p].stages) {
+                o << (st.mfma ? "mfma" : !st.U.empty() ? "dense" : "stage") << " {";
+                for (size_t i = 0; i < st.tbits.size(); ++i) o << (i ? " " : "") << passes[p].qlist[st.tbits[i]];
+                o << "}: " << st.ops.size() << " ops\\l";
+            }
+            o << "\"];\n";
+            nodes.push_back(id);
+            seg_of.push_back(s);
+        }
+        o << "  }\n";
+    }
+    for (size_t i = 1; i < nodes.size(); ++i) {
+        o << "  " << nodes[i - 1] << " -> " << nodes[i];
+        if (seg_of[i] != seg_of[i - 1])
+            o << " [label=\"" << (stores_ckpt(seg_of[i], S) ? "checkpoint" : "boundary") << "\", style=bold]";
+        o << ";\n";
+    }
+    o << "}\n";
+    return o.str();
+}
+
 int Session::dump(const char *path) {
+    const size_t len = std::strlen(path);
+    if (len >= 4 && std::strcmp(path + len - 4, ".dot") == 0) {
+        FILE *f = std::fopen(path, "w");
+        if (!f) return QTASK_E_ARG;
+        const std::string dot = plan_dot();
+        const size_t wr = std::fwrite(dot.data(), 1, dot.size(), f);
+        std::fclose(f);
+        return wr == dot.size() ? QTASK_OK : QTASK_E_ARG;
+    }
     std::ostringstream o;
     o << "{\"n\":" << n << ",\"n_buffer\":" << n_int << ",\"dtype\":" << dtype << ",\"levels\":" << circ.num_levels()
       << ",\"gates\":" << circ.num_gates() << ",\"tile_bits\":" << opts.tile_bits << ",\"low_bits\":" << opts.low_bits

@@ -50,6 +50,7 @@ public:
     int read(uint64_t first, uint64_t count, void *out);
     int norm(double *out);
     int hash(uint64_t *out);
+    std::string plan_dot() const;
     int dump(const char *path);
     uint64_t device_bytes() const;
     uint64_t state_bytes() const { return (uint64_t(1) << n_int) * elem; }

@@ -466,6 +466,31 @@ def test_segments_survive_a_full_rerun_after_level_removal():
                 assert json.dumps(sim.dump()["segments"]) == inc
 
 
+def test_plan_dump_as_graphviz(tmp_path):
+    """A dump path ending in .dot gives the pass graph: one cluster per
+    segment, one node per pass (the same passes as the JSON dump), edges in
+    execution order, and the segment boundaries marked as checkpoints."""
+    wl = W.config(2, n=12, levels=20, batches=1)
+    with plan_only(12, ckpt_interval=8, tile_bits=8, low_bits=3) as sim:
+        sim.build(wl.nets)
+        sim.update()
+        segs = sim.dump()["segments"]
+        path = str(tmp_path / "plan.dot")
+        Q.qtask_dump_plan(sim.h, path)
+        txt = open(path).read()
+    assert txt.startswith("digraph qtask {") and txt.rstrip().endswith("}")
+    n_pass = sum(len(s["passes"]) for s in segs)
+    assert txt.count("subgraph cluster_s") == len(segs)
+    assert len(re.findall(r'p\d+_\d+ \[label="pass', txt)) == n_pass
+    assert len(re.findall(r"p\d+_\d+ -> p\d+_\d+", txt)) == n_pass - 1
+    assert txt.count('label="checkpoint"') == len(segs) - 1
+    for s, seg in enumerate(segs):
+        for p, ps in enumerate(seg["passes"]):
+            line = next(l for l in txt.splitlines() if l.strip().startswith("p%d_%d [" % (s, p)))
+            assert "qubits " + " ".join(str(q) for q in ps["qubits"]) in line
+            assert line.count("ops\\l") == len(ps["stages"])
+
+
 def test_server_opts_and_edit_records():
     o = Q.qtask_server_opts_default()
     assert o.struct_size == Q.ctypes.sizeof(Q.qtask_server_opts)
