@@ -165,7 +165,9 @@ int Session::autotune() {
         last_error = "autotune: device error";
         return rc;
     }
-    const std::vector<double> &score = seg.size() > ops.size() && finalists.size() > 1 ? t2 : t1;
+    bool round2 = false;  // ran, and some finalist planned on the whole segment
+    for (size_t i : finalists) round2 = round2 || t2[i] < 1e300;
+    const std::vector<double> &score = round2 ? t2 : t1;
     // A later candidate (larger tile, then more fixed low bits) must be
     // clearly faster: within 1% -- about the spread of two timings of one
     // plan -- the earlier one is kept.  The pick is then the same from run to
