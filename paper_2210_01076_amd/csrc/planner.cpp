@@ -39,24 +39,53 @@ uint32_t bank_vec(int p, int swz) {
 
 int popc(uint64_t x) { return __builtin_popcountll(x); }
 
-// Order `bits` so the first ones have linearly independent bank vectors
-// (they become the low lane bits), then the rest ascending.
-std::vector<int> lane_order(const std::vector<int> &bits, int swz) {
-    std::vector<int> first, rest;
-    uint32_t basis[32] = {0};  // GF(2) echelon basis indexed by leading bit
-    for (int p : bits) {
-        uint32_t v = bank_vec(p, swz);
-        for (int lead = 31; lead >= 0 && v; --lead)
-            if (((v >> lead) & 1) && basis[lead]) v ^= basis[lead];
-        if (v != 0 && int(first.size()) < swz) {
-            basis[31 - __builtin_clz(v)] = v;
-            first.push_back(p);
-        } else {
-            rest.push_back(p);
+// LDS banking as the hardware serves a wave (measured with bank-conflict
+// counters): a 16-byte read serves 16 lanes per cycle from 256 bytes of
+// banks, a 16-byte write 8 lanes from 128 bytes; an 8-byte read 32 lanes from
+// 256 bytes, an 8-byte write 16 lanes from 128 bytes.  With slots of
+// 2^(4 or 3) bytes, a read is conflict free when the slots of its lane group
+// differ in their low `swz` bits and a write when they differ in their low
+// swz - 1 bits, i.e. when the bank vectors of the first swz (swz - 1) lane
+// bits are linearly independent in those bits.
+//
+// Order `bits` as lane bits after the fixed lowest lane bits `prefix` (which
+// come first, in order): it greedily takes bits whose bank vectors extend an
+// independent set, first in the low swz - 1 bits (writes) and then in all
+// swz bits (reads), and puts the remaining bits after them in their given
+// order.
+std::vector<int> lane_order(const std::vector<int> &bits, int swz, const std::vector<int> &prefix = {}) {
+    std::vector<int> out(prefix);
+    std::vector<int> pool;
+    for (int p : bits)
+        if (std::find(prefix.begin(), prefix.end(), p) == prefix.end()) pool.push_back(p);
+    // independent-set test by GF(2) elimination against the vectors so far
+    auto independent = [&](const std::vector<int> &chosen, int p, uint32_t mask) {
+        uint32_t basis[32] = {0};
+        auto insert = [&](uint32_t v) {
+            for (int lead = 31; lead >= 0 && v; --lead)
+                if ((v >> lead) & 1) {
+                    if (!basis[lead]) { basis[lead] = v; return true; }
+                    v ^= basis[lead];
+                }
+            return false;
+        };
+        for (int q : chosen) insert(bank_vec(q, swz) & mask);
+        return insert(bank_vec(p, swz) & mask);
+    };
+    for (int level = 0; level < 2; ++level) {
+        const int want = level == 0 ? swz - 1 : swz;
+        const uint32_t mask = (1u << want) - 1;
+        for (size_t i = 0; i < pool.size() && int(out.size()) < want;) {
+            if (independent(out, pool[i], mask)) {
+                out.push_back(pool[i]);
+                pool.erase(pool.begin() + long(i));
+            } else {
+                ++i;
+            }
         }
     }
-    first.insert(first.end(), rest.begin(), rest.end());
-    return first;
+    out.insert(out.end(), pool.begin(), pool.end());
+    return out;
 }
 
 bool mergeable(const LGate &g) {
@@ -273,9 +302,9 @@ struct Packer {
         }
     }
 
-    // Every pass has at least one stage, and its first and last stages use
-    // ascending thread-bit order: their thread bits then start at the lowest
-    // tile bits, which keeps their global loads and stores coalesced.
+    // Every pass has at least one stage, and the lowest lane bits of its
+    // first and last stages are the lowest tile bits, which keeps their
+    // global loads and stores coalesced.
     // tile bits that must vary across lanes for coalesced 128-byte segments
     int coalesce_bits() const { return pp.dtype == 0 ? 3 : 4; }
 
@@ -299,10 +328,14 @@ struct Packer {
         if (ps.stages.back().mfma || (ps.stages.size() > 1 && touches_low(ps.stages.back())))
             ps.stages.push_back(empty_stage());
         for (const auto &st : ps.stages) ps.has_mfma = ps.has_mfma || st.mfma;
+        // their lowest lane bits are the lowest tile bits, in order (what
+        // coalescing needs); the next ones are chosen for the banks
         for (PStage *st : {&ps.stages.front(), &ps.stages.back()}) {
-            st->tpos.clear();
+            std::vector<int> others, low;
             for (int p = 0; p < pp.b; ++p)
-                if (std::find(st->tbits.begin(), st->tbits.end(), p) == st->tbits.end()) st->tpos.push_back(p);
+                if (std::find(st->tbits.begin(), st->tbits.end(), p) == st->tbits.end()) others.push_back(p);
+            for (int p = 0; p < lowb && p < int(others.size()) && others[p] == p; ++p) low.push_back(p);
+            st->tpos = lane_order(others, pp.swz, low);
         }
     }
 
@@ -711,6 +744,10 @@ std::string plan_json(const SegmentPlan &sp, bool with_matrices) {
             if (si) o << ",";
             o << "{\"qubits\":[";
             for (size_t i = 0; i < st.tbits.size(); ++i) o << (i ? "," : "") << ps.qlist[st.tbits[i]];
+            o << "],\"reg_tile_bits\":[";
+            for (size_t i = 0; i < st.tbits.size(); ++i) o << (i ? "," : "") << st.tbits[i];
+            o << "],\"lane_tile_bits\":[";
+            for (size_t i = 0; i < st.tpos.size(); ++i) o << (i ? "," : "") << st.tpos[i];
             o << "],\"mfma\":" << (st.mfma ? "true" : "false") << ",\"dense\":" << (st.U.empty() ? "false" : "true")
               << ",\"flops_per_amp\":" << st.flops << ",\"ops\":[";
             for (size_t k = 0; k < st.ops.size(); ++k) {
