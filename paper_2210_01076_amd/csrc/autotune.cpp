@@ -136,7 +136,7 @@ int Session::autotune() {
         return r;
     };
 
-    // Round 1: every candidate on the prefix, twice (a first run well behind
+    // Screening: every candidate on the prefix, twice (a first run well behind
     // the best so far cannot win and skips the second).
     std::vector<double> t1(cand.size(), 1e300);
     double best1 = 1e300;
@@ -145,7 +145,7 @@ int Session::autotune() {
         if (rc != QTASK_OK) break;
         best1 = std::min(best1, t1[i]);
     }
-    // Round 2: the three fastest on the whole first segment.  The prefix ends
+    // Final timing: the three fastest on the whole first segment.  The prefix ends
     // in a partly filled pass whose share differs between shapes by up to one
     // pass in twenty; over the segment that error is a few times smaller.
     std::vector<size_t> order(cand.size());
@@ -165,9 +165,9 @@ int Session::autotune() {
         last_error = "autotune: device error";
         return rc;
     }
-    bool round2 = false;  // ran, and some finalist planned on the whole segment
-    for (size_t i : finalists) round2 = round2 || t2[i] < 1e300;
-    const std::vector<double> &score = round2 ? t2 : t1;
+    bool timed_finals = false;  // ran, and some finalist planned on the whole segment
+    for (size_t i : finalists) timed_finals = timed_finals || t2[i] < 1e300;
+    const std::vector<double> &score = timed_finals ? t2 : t1;
     // A later candidate (larger tile, then more fixed low bits) must be
     // clearly faster: within 1% -- about the spread of two timings of one
     // plan -- the earlier one is kept.  The pick is then the same from run to
