@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle
+from paper_2210_01076_amd import qtask as Q
 from paper_2210_01076_amd import workloads as W
 from tests.gpu_util import bytes_equal, check_state, log, sim
 
@@ -263,13 +264,14 @@ def test_edit_sequences_with_level_removals_and_merged_phases(seed):
     _edit_sequence(12, nets, kinds, "c128", 2 + seed % 4, np.random.default_rng(seed), 25)
 
 
-@pytest.mark.parametrize("block", range(4))
+@pytest.mark.parametrize("block", range(6))
 def test_random_shapes_and_dtypes_stay_bitwise_equal(block):
     """Random edit sequences over random session shapes: 8-14 qubits, tile
     bits 4-10, low bits, tracker block bits 1-6, checkpoint intervals 1-6,
     both dtypes and four circuit families.  After every update the state
     equals a full re-simulation bit for bit; at the end it matches the
-    oracle."""
+    oracle.  The last two blocks fuse every stage into a dense unitary (on
+    the matrix cores where the tile allows it)."""
     for seed in range(block * 10, block * 10 + 10):
         rng = np.random.default_rng(100000 + seed)
         n = int(rng.integers(8, 15))
@@ -282,8 +284,15 @@ def test_random_shapes_and_dtypes_stay_bitwise_equal(block):
         nets, kinds = _edit_family(family, n, seed)
         if family == "dense":
             kinds = ("h", "x", "y", "cx", "cz", "rz", "rx", "swap", "t", "sdg", "ccx", "ry", "cp")
-        log("seed %d: %s %s n=%d K=%d b=%d c=%d block_bits=%d" % (seed, family, dtype, n, K, b, c, bb))
-        with sim(n, nets, dtype, ckpt_interval=K, block_bits=bb, tile_bits=b, low_bits=c) as s:
+        fo = {}
+        if block >= 4:
+            k = int(rng.integers(4, 7))
+            if b >= 10 and b - k >= 4:
+                fo = dict(fusion=Q.QTASK_FUSE_DENSE, fuse_width=k)
+            elif b >= 8:
+                fo = dict(fusion=Q.QTASK_FUSE_DENSE, fuse_width=4)
+        log("seed %d: %s %s n=%d K=%d b=%d c=%d block_bits=%d %s" % (seed, family, dtype, n, K, b, c, bb, fo))
+        with sim(n, nets, dtype, ckpt_interval=K, block_bits=bb, tile_bits=b, low_bits=c, **fo) as s:
             s.update()
             for step in range(15):
                 if rng.random() < 0.15 and len(nets) > 2:
