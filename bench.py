@@ -514,6 +514,9 @@ def main():
                     help="pin the complex128 tier's tile bits instead of autotuning (profiling runs: counter "
                          "collection slows kernels and would sway the tuner's timings)")
     ap.add_argument("--low-bits", type=int, default=3, help="contiguous low bits with --tile-bits")
+    ap.add_argument("--c64-tile-bits", type=int, default=0, help="the same for the complex64 tier")
+    ap.add_argument("--c64-low-bits", type=int, default=4, help="contiguous low bits with --c64-tile-bits")
+    ap.add_argument("--traffic-c64", default=os.path.join(ROOT, "profiles", "traffic_layered_n24_c64.json"))
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -545,7 +548,8 @@ def main():
     sim128, nets, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup, shape)
     r64 = None
     if not args.no_c64:
-        sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup)
+        shape64 = (args.c64_tile_bits, args.c64_low_bits) if args.c64_tile_bits else None
+        sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup, shape64)
         import numpy as np
         a = sim128.state()
         b = sim64.state().astype(np.complex128)
@@ -608,13 +612,20 @@ def main():
 
     # HBM bytes per launch from the committed counter summary, dropped once
     # the kernel source no longer matches the one the counters were taken on
-    traffic = None
-    if os.path.exists(args.traffic):
+    def load_traffic(path):
+        if not os.path.exists(path):
+            return None
         from paper_2210_01076_amd import profiling
-        with open(args.traffic) as f:
+        with open(path) as f:
             rec = json.load(f)
-        if rec.get("kernel_source_hash") == profiling.kernel_source_hash():
-            traffic = rec.get("hbm_bytes_per_launch")
+        if rec.get("kernel_source_hash") != profiling.kernel_source_hash():
+            return None
+        return rec.get("hbm_bytes_per_launch")
+
+    traffic = load_traffic(args.traffic)
+    if r64 is not None:
+        # the complex64 pass kernel's HBM bytes per launch, from its own summary
+        r64["traffic"] = load_traffic(args.traffic_c64)
     achieved = r128["launch_bytes"] / (r128["launch_ms"] * 1e-3) / 1e9
     line = {
         "metric": "full-sim HBM GB/s vs peak; incremental update p50/p99 latency and speedup vs full re-sim",

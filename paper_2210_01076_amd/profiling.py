@@ -93,12 +93,23 @@ def _bench_line(path):
         return json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
 
 
-def summarize(trace, fetch, write, bench_json, counter_bench_json, copy_bytes, command, kernel, copy_kernel):
+def _tier(bench, tier):
+    """Pass-launch figures of one tier of a benchmark line: the complex128
+    tier's are its roofline record, the complex64 tier's its own record."""
+    if tier == "c128":
+        return bench["roofline"]
+    r = bench["c64"]
+    return {"bytes_per_launch": r["launch_bytes"], "launches_timed": r["launches"], "avg_launch_ms": r["launch_ms"],
+            "block": 1 << (r["tile_bits"] - 4)}
+
+
+def summarize(trace, fetch, write, bench_json, counter_bench_json, copy_bytes, command, kernel, copy_kernel,
+              tier="c128"):
     bench = _bench_line(bench_json)
     cbench = _bench_line(counter_bench_json)
-    counter_launches = cbench["roofline"]["launches_timed"]
-    counter_alg = cbench["roofline"]["bytes_per_launch"]
-    roof = bench["roofline"]
+    counter_launches = _tier(cbench, tier)["launches_timed"]
+    counter_alg = _tier(cbench, tier)["bytes_per_launch"]
+    roof = _tier(bench, tier)
     block, n_timed = roof["block"], roof["launches_timed"]
     stats = kernel_stats(trace)
     durs = dispatches(trace, kernel, block)[-n_timed:]
@@ -137,6 +148,8 @@ def summarize(trace, fetch, write, bench_json, counter_bench_json, copy_bytes, c
         "kernel_source_hash": kernel_source_hash(),
         "command": command,
     }
+    if tier != "c128":
+        rec["workload"] = rec["workload"].replace("complex128", "complex64 tier")
     lines = ["# %s -- %s" % (kernel, rec["workload"]), ""]
     for k, v in command.items():
         lines.append("%s: %s" % (k, v))
@@ -245,6 +258,8 @@ def main():
     ap.add_argument("--counter-bench-json", required=True, help="output of the counter benchmark runs")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--kernel", default="qk_pass<double, false>")
+    ap.add_argument("--tier", default="c128", choices=["c128", "c64"],
+                    help="which tier of the benchmark line the pass launches belong to")
     ap.add_argument("--copy-kernel", default="qk_copy")
     ap.add_argument("--cmd-trace", default="")
     ap.add_argument("--cmd-fetch", default="")
@@ -254,7 +269,7 @@ def main():
     a = ap.parse_args()
     command = {"trace": a.cmd_trace, "fetch": a.cmd_fetch, "write": a.cmd_write}
     rec, txt = summarize(a.trace, a.fetch, a.write, a.bench_json, a.counter_bench_json, a.copy_bytes, command,
-                         a.kernel, a.copy_kernel)
+                         a.kernel, a.copy_kernel, a.tier)
     with open(a.out_txt, "w") as f:
         f.write(txt)
     with open(a.out_json, "w") as f:
