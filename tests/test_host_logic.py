@@ -491,6 +491,28 @@ def test_plan_dump_as_graphviz(tmp_path):
             assert line.count("ops\\l") == len(ps["stages"])
 
 
+def test_abi_from_plain_c(tmp_path):
+    """A C11 program includes the header and links the library directly:
+    the modifier, update and query cycle of a plan-only session, with the
+    documented status codes."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.dirname(Q.LIB_PATH)
+    exe = str(tmp_path / "abi")
+    subprocess.run([cc, "-std=c11", "-Wall", "-Werror", "-I", os.path.join(root, "include"),
+                    os.path.join(root, "tests", "abi_plan_only.c"), "-L", libdir, "-lqtask",
+                    "-Wl,-rpath," + libdir, "-o", exe], check=True)
+    dot = str(tmp_path / "plan.dot")
+    out = subprocess.run([exe, dot], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "FAIL" not in out.stdout and out.stdout.count("ok ") >= 20
+    assert open(dot).read().startswith("digraph qtask {")
+
+
 def test_server_opts_and_edit_records():
     o = Q.qtask_server_opts_default()
     assert o.struct_size == Q.ctypes.sizeof(Q.qtask_server_opts)
