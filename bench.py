@@ -246,6 +246,50 @@ def run_append(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10):
             "mismatches": mismatches, "compared_depths": len(pairs)}
 
 
+def run_small(Q, W, repeats=20):
+    """The 10-qubit dense random circuit (20 levels, 10 single-gate
+    modifiers): the whole state (16 KiB) is one tile, so this is launch
+    latency, not bandwidth.  Wall time of each call (host planning, launches
+    and the wait), per modifier for the incremental update and for a full
+    re-simulation of the same circuit, compared by hash."""
+    wl = W.config(1)
+    nets = [list(x) for x in wl.nets]
+    first, inc, full, mismatches = [], [], [], 0
+    for _ in range(repeats):
+        s = Q.Simulator(wl.n, "c128", device=0, ckpt_interval=5)
+        try:
+            s.build(nets)
+            first.append(s.update()["wall_ms"])
+        finally:
+            s.close()
+    s = Q.Simulator(wl.n, "c128", device=0, ckpt_interval=5)
+    work = [list(x) for x in nets]
+    try:
+        s.build(work)
+        s.update()
+        for _ in range(repeats // 2):
+            for batch in wl.batches:
+                for e in batch:
+                    W.apply_edit(work, e)
+                    s.apply_edit(e)
+                inc.append(s.update()["wall_ms"])
+                h = s.hash()
+                full.append(s.update(full=True)["wall_ms"])
+                mismatches += int(s.hash() != h)
+            # undo: replaying the same batches again needs the original circuit
+            s.close()
+            s = Q.Simulator(wl.n, "c128", device=0, ckpt_interval=5)
+            work = [list(x) for x in nets]
+            s.build(work)
+            s.update()
+    finally:
+        s.close()
+    return {"workload": "dense random circuit, 10 qubits, 20 levels, 10 single-gate modifiers; complex128",
+            "first_update_us_p50": 1e3 * pct(first, 50),
+            "update_us_p50": 1e3 * pct(inc, 50), "update_us_p99": 1e3 * pct(inc, 99),
+            "full_us_p50": 1e3 * pct(full, 50), "updates": len(inc), "mismatches": mismatches}
+
+
 def run_protocols(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10, mixes=50, seed=77):
     """The paper's other incremental protocols on the same circuit (Section
     IV): insert the nets one at a time in random order until the circuit is
@@ -561,6 +605,10 @@ def main():
     # before the serving leg: autotuner picks are cached per (qubits, dtype,
     # gate mix), and the serving sessions tune while other sessions run, so
     # a 28-qubit pick made there would be timed under contention
+    small = run_small(Q, W)
+    log("10-qubit circuit: update p50 %.0f us p99 %.0f us, full re-simulation p50 %.0f us, mismatches %d" % (
+        small["update_us_p50"], small["update_us_p99"], small["full_us_p50"], small["mismatches"]))
+
     large = None
     if not args.no_large:
         large = run_large(Q, W)
@@ -667,6 +715,7 @@ def main():
                              "256 MB Infinity Cache; large_state is the HBM-only figure (28 qubits, 4 GiB)"},
         "append_protocol": append,
         "other_protocols": protocols,
+        "small_circuit": small,
         "large_state": large,
         "fused_dense": fused,
         "serving": serving,

@@ -100,7 +100,7 @@ typedef struct qtask_opts {
     int32_t renorm;         /* C64: renormalise at every segment end (default 1) */
     int32_t autotune;       /* 1: time candidate (tile_bits, low_bits) at the first update and keep the fastest
                                (every candidate on a prefix of about 600 gates, the three fastest again on the
-                               first segment; within 1% the smaller tile wins); under QTASK_FUSE_AUTO the
+                               first segments, about 3000 gates; within 1% the smaller tile wins); under QTASK_FUSE_AUTO the
                                candidates also include dense fusion at fuse_width 4..6, and the pick sets fusion
                                and fuse_width.  The pick is cached per process and frozen for the session */
     int32_t closed_mode;    /* 1 (default): replay only affected blocks when the affected set is closed */

@@ -6,8 +6,8 @@
 // instead: at the first update of a session it plans the circuit's first
 // levels with every candidate, runs each plan on the device (twice, keeping
 // the second timing, unless the first is already well behind), times the
-// three fastest again on the whole first segment, and keeps the fastest of
-// those (near-ties go to the smaller tile).  The pick is cached per
+// three fastest again on the circuit's first segments (about 3000 gates),
+// and keeps the fastest of those (near-ties go to the smaller tile).  The pick is cached per
 // (device, state qubits, dtype, requested fusion mode and width, gate mix)
 // and frozen for the session, so every later plan of the session, full or
 // incremental, uses the same shape and results stay bitwise reproducible.
@@ -40,18 +40,23 @@ int Session::autotune() {
     if (plan_only) return QTASK_OK;
     int rc = init_device();
     if (rc != QTASK_OK) return rc;
-    // the circuit's first segment (at most ~3000 gates) and its prefix of at
-    // most ~600 gates
-    std::vector<LGate> seg, ops;
+    // the circuit's first segments of K levels (as a fresh circuit is cut),
+    // about 3000 gates in all, and the prefix of the first segment that
+    // ends with the level reaching 600 gates
+    std::vector<std::vector<LGate>> segs(1);
+    std::vector<LGate> ops;
+    size_t total = 0;
     {
-        const size_t D = circ.num_levels();
-        for (size_t li = 0; li < D && li < size_t(K()) && seg.size() < 3000; ++li) {
+        const size_t D = circ.num_levels(), Kz = size_t(K());
+        for (size_t li = 0; li < D && total < 3000; ++li) {
+            if (li > 0 && li % Kz == 0) segs.emplace_back();
             const Level &lv = circ.level_by_index(li);
             for (uint64_t gid : lv.gates) {
                 const Gate &g = circ.gate(gid);
-                seg.push_back(lower_gate(g.kind, g.q, g.p, g.id));
+                segs.back().push_back(lower_gate(g.kind, g.q, g.p, g.id));
+                ++total;
             }
-            if (ops.size() < 600) ops = seg;  // the prefix ends with the level that reaches 600
+            if (li < Kz && ops.size() < 600) ops = segs.front();
         }
     }
     if (ops.empty()) return QTASK_OK;
@@ -87,10 +92,12 @@ int Session::autotune() {
     if (cand.empty())
         cand.push_back({std::min(opts.tile_bits, n_int), std::min(opts.low_bits, n_int), opts.fusion, opts.fuse_width});
 
-    // Device time of one candidate's plan of `gates`, run `reps` times (the
-    // last run counts; a run slower than `cutoff` ms ends the repetitions).
-    // A candidate the planner rejects gets +inf.
-    auto time_plan = [&](const std::vector<LGate> &gates, const Cand &bc, int reps, double cutoff, double &out) {
+    // Device time of one candidate's plans of `parts` (segments, run in
+    // order), run `reps` times (the last run counts; a run slower than
+    // `cutoff` ms ends the repetitions).  A candidate the planner rejects
+    // gets +inf.
+    auto time_plan = [&](const std::vector<std::vector<LGate>> &parts, const Cand &bc, int reps, double cutoff,
+                         double &out) {
         out = 1e300;
         PlanParams pp;
         pp.n = n_int;
@@ -100,38 +107,43 @@ int Session::autotune() {
         pp.fusion = bc.fusion;
         pp.fuse_k = bc.k;
         pp.swz = dtype == QTASK_C128 ? 4 : 5;
-        SegmentPlan sp;
+        std::vector<SegmentPlan> sps(parts.size());
         try {
-            sp = plan_segment(gates, pp);
+            for (size_t i = 0; i < parts.size(); ++i) sps[i] = plan_segment(parts[i], pp);
         } catch (const std::exception &e) {
             return QTASK_OK;
         }
-        int r = upload_plan(sp);
-        if (r != QTASK_OK) return r;
+        int r = QTASK_OK;
+        size_t uploaded = 0;
+        for (; uploaded < sps.size() && r == QTASK_OK; ++uploaded) r = upload_plan(sps[uploaded]);
         float ms = 0;
         for (int rep = 0; rep < reps && r == QTASK_OK; ++rep) {
             if (rep > 0 && ms > cutoff) break;
             if (hipEventRecord(ev0_, stream) != hipSuccess) r = QTASK_E_DEVICE;
-            const char *blob = static_cast<const char *>(sp.dev);
-            for (size_t p = 0; p < sp.passes.size() && r == QTASK_OK; ++p) {
-                KArgs a{};
-                a.dst = state_.p;
-                a.src = p == 0 ? nullptr : state_.p;
-                a.src_basis = p == 0 ? 1 : 0;
-                a.pass = reinterpret_cast<const KPass *>(blob) + p;
-                a.stages = reinterpret_cast<const KStage *>(blob + sp.off_stage);
-                a.ops = reinterpret_cast<const KOp *>(blob + sp.off_op);
-                a.coefs = blob + sp.off_coef;
-                a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
-                if (launch_pass(dtype, a, uint32_t(uint64_t(1) << (n_int - pp.b)), pp.b, stream) != hipSuccess)
-                    r = QTASK_E_DEVICE;
+            bool first = true;
+            for (const SegmentPlan &sp : sps) {
+                const char *blob = static_cast<const char *>(sp.dev);
+                for (size_t p = 0; p < sp.passes.size() && r == QTASK_OK; ++p) {
+                    KArgs a{};
+                    a.dst = state_.p;
+                    a.src = first ? nullptr : state_.p;
+                    a.src_basis = first ? 1 : 0;
+                    a.pass = reinterpret_cast<const KPass *>(blob) + p;
+                    a.stages = reinterpret_cast<const KStage *>(blob + sp.off_stage);
+                    a.ops = reinterpret_cast<const KOp *>(blob + sp.off_op);
+                    a.coefs = blob + sp.off_coef;
+                    a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
+                    if (launch_pass(dtype, a, uint32_t(uint64_t(1) << (n_int - pp.b)), pp.b, stream) != hipSuccess)
+                        r = QTASK_E_DEVICE;
+                    first = false;
+                }
             }
             if (r == QTASK_OK && (hipEventRecord(ev1_, stream) != hipSuccess ||
                                   hipStreamSynchronize(stream) != hipSuccess ||
                                   hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
                 r = QTASK_E_DEVICE;
         }
-        dfree(sp.dev);
+        for (size_t i = 0; i < uploaded; ++i) dfree(sps[i].dev);
         if (r == QTASK_OK) out = ms;
         return r;
     };
@@ -141,11 +153,12 @@ int Session::autotune() {
     std::vector<double> t1(cand.size(), 1e300);
     double best1 = 1e300;
     for (size_t i = 0; i < cand.size(); ++i) {
-        rc = time_plan(ops, cand[i], 2, 1.3 * best1, t1[i]);
+        rc = time_plan({ops}, cand[i], 2, 1.3 * best1, t1[i]);
         if (rc != QTASK_OK) break;
         best1 = std::min(best1, t1[i]);
     }
-    // Final timing: the three fastest on the whole first segment.  The prefix ends
+    // Final timing: the three fastest on the first segments (about 3000
+    // gates), twice each (the second run counts).  The prefix ends
     // in a partly filled pass whose share differs between shapes by up to one
     // pass in twenty; over the segment that error is a few times smaller.
     std::vector<size_t> order(cand.size());
@@ -156,9 +169,9 @@ int Session::autotune() {
         if (finalists.size() < 3 && t1[i] < 1e300) finalists.push_back(i);
     std::sort(finalists.begin(), finalists.end());  // back to candidate order
     std::vector<double> t2(cand.size(), 1e300);
-    if (rc == QTASK_OK && seg.size() > ops.size() && finalists.size() > 1)
+    if (rc == QTASK_OK && total > ops.size() && finalists.size() > 1)
         for (size_t i : finalists) {
-            rc = time_plan(seg, cand[i], 1, 0, t2[i]);
+            rc = time_plan(segs, cand[i], 2, 1e300, t2[i]);
             if (rc != QTASK_OK) break;
         }
     if (rc != QTASK_OK) {
