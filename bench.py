@@ -485,7 +485,7 @@ def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 <<
     return out
 
 
-def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=40):
+def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=150):
     """Time the CPU oracle (all host threads) on the first nets of the same
     circuit, adding nets until about min_s seconds of work."""
     from oracle import oracle
