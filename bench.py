@@ -125,14 +125,14 @@ def run_tier(Q, W, wl, dtype, steps, warmup, shape=None):
     return sim, nets, out
 
 
-def run_serving(Q, W, dtype, specs, keep_n=20):
+def run_serving(Q, W, dtype, specs, keep_n=20, order=0):
     """Serve the sessions on one device: open all, run each one's initial
     simulation (warm-up, untimed), then replay the Poisson request stream at
     its arrival times and report request latency and throughput."""
     import threading
 
     dt = Q.QTASK_C128 if dtype == "c128" else Q.QTASK_C64
-    sv = Q.qtask_server_create(Q.qtask_server_opts_default())
+    sv = Q.qtask_server_create(Q.qtask_server_opts_default(order=order))
     try:
         t0 = time.perf_counter()
         sids = [Q.qtask_server_open(sv, s.n, dt, Q.qtask_opts_default(device=0), s.nets) for s in specs]
@@ -624,9 +624,20 @@ def main():
         errs = [float(np.max(np.abs(kept128[i] - kept64[i].astype(np.complex128)))) for i in kept128 if i in kept64]
         s64["max_abs_vs_c128"] = max(errs) if errs else None
         s64["compared_sessions"] = len(errs)
+        # the same streams with the expected-shortest request started first
+        sf = {}
+        for dt in ("c128", "c64"):
+            r, _ = run_serving(Q, W, dt, specs, keep_n=0, order=1)
+            sf[dt] = {k: r[k] for k in ("latency_ms_p50", "latency_ms_p99", "service_ms_p50", "updates_per_s",
+                                        "failed")}
         serving = {"workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels, "
                                "Poisson requests of 1-3 edits (4 per session); sessions under 16 qubits batched",
-                   "c128": s128, "c64": s64}
+                   "order": "oldest request first",
+                   "c128": s128, "c64": s64,
+                   "shortest_first": sf}
+        log("serving, expected-shortest first: c128 p50 %.1f ms p99 %.1f ms | c64 p50 %.1f ms p99 %.1f ms" % (
+            sf["c128"]["latency_ms_p50"], sf["c128"]["latency_ms_p99"],
+            sf["c64"]["latency_ms_p50"], sf["c64"]["latency_ms_p99"]))
         log("serving c128 p50 %.1f ms p99 %.1f ms %.1f upd/s | c64 p50 %.1f ms p99 %.1f ms %.1f upd/s" % (
             s128["latency_ms_p50"], s128["latency_ms_p99"], s128["updates_per_s"],
             s64["latency_ms_p50"], s64["latency_ms_p99"], s64["updates_per_s"]))

@@ -234,6 +234,9 @@ typedef struct qtask_server_opts {
     int32_t max_inflight;     /* large sessions updating at once */
     int32_t small_qubits;     /* sessions with n < small_qubits go through the batched graph launch (default 16) */
     int32_t use_graph;        /* 1 (default): capture the batched launch in a HIP graph */
+    int32_t order;            /* which waiting request starts first: 0 (default) the oldest; 1 the one whose
+                                 update is expected to be shortest (2^n times the session's levels), that
+                                 estimate divided by 1 + waiting time / 1 s so that no request waits for ever */
 } qtask_server_opts;
 
 typedef struct qtask_edit {

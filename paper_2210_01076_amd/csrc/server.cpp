@@ -17,7 +17,10 @@
 //  - Requests that arrive while a tick or a large update runs join the next
 //    tick (continuous batching); every result carries submit/start/done
 //    stamps and the state hash.
+//  - Waiting requests start oldest first, or (order 1) expected-shortest
+//    first, the estimate 2^n x levels divided by 1 + waiting time / 1 s.
 #include <algorithm>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -51,6 +54,9 @@ struct Request {
     std::vector<qtask_edit> edits;
     double submit_ms = 0;
 };
+
+// waiting time that halves a request's expected-cost key under order 1
+constexpr double kAgingMs = 1000.0;
 
 struct SSession {
     Session *s = nullptr;
@@ -384,8 +390,20 @@ void qtask_server_s::run() {
             std::vector<int32_t> order;
             for (size_t i = 0; i < sess.size(); ++i)
                 if (!sess[i].busy && !sess[i].q.empty()) order.push_back(int32_t(i));
-            std::sort(order.begin(), order.end(),
-                      [&](int32_t a, int32_t b) { return sess[a].q.front().submit_ms < sess[b].q.front().submit_ms; });
+            // oldest first, or expected-shortest first with the estimate
+            // discounted by waiting time (only the worker touches a session's
+            // circuit, so reading its size here is safe)
+            const double now = clock();
+            auto key = [&](int32_t sid) {
+                const SSession &ss = sess[sid];
+                const double submit = ss.q.front().submit_ms;
+                if (opts.order == 0) return submit;
+                const double cost = std::ldexp(double(std::max<size_t>(1, ss.s->circ.num_levels())), ss.s->n_int);
+                return cost / (1.0 + std::max(0.0, now - submit) / kAgingMs);
+            };
+            std::vector<std::pair<double, double>> keys(sess.size());
+            for (int32_t sid : order) keys[size_t(sid)] = {key(sid), sess[sid].q.front().submit_ms};
+            std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return keys[size_t(a)] < keys[size_t(b)]; });
             for (int32_t sid : order) {
                 SSession &ss = sess[sid];
                 if (!ss.small && inflight_large >= opts.max_inflight) continue;
@@ -511,7 +529,7 @@ int qtask_server_create(const qtask_server_opts *user, qtask_server_t *out) {
         if (user->struct_size != sizeof(qtask_server_opts)) return QTASK_E_ARG;
         o = *user;
     }
-    if (o.max_inflight < 1 || o.small_qubits < 0 || o.device < 0) return QTASK_E_ARG;
+    if (o.max_inflight < 1 || o.small_qubits < 0 || o.device < 0 || o.order < 0 || o.order > 1) return QTASK_E_ARG;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || o.device >= count) {
         (void)hipGetLastError();

@@ -58,7 +58,7 @@ class qtask_stats(ctypes.Structure):
 
 class qtask_server_opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("device", i32), ("budget_bytes", u64),
-                ("max_inflight", i32), ("small_qubits", i32), ("use_graph", i32)]
+                ("max_inflight", i32), ("small_qubits", i32), ("use_graph", i32), ("order", i32)]
 
 
 class qtask_edit(ctypes.Structure):

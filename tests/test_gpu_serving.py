@@ -93,19 +93,22 @@ def test_small_sessions_alone_equals_mix(use_graph):
     log("small mix ok, usage", usage)
 
 
-def test_mixed_sizes_alone_equals_mix():
-    """Small batched sessions beside large ones on their own streams."""
+@pytest.mark.parametrize("order", [0, 1])
+def test_mixed_sizes_alone_equals_mix(order):
+    """Small batched sessions beside large ones on their own streams, with
+    requests started oldest first or expected-shortest first."""
     small = _specs(77, 6, 8, 14, 10, 2)
     large = _specs(88, 3, 17, 19, 10, 2)
     specs = small + large
     opts = dict(ckpt_interval=4)
     alone = [_alone(n, d, nets, reqs, opts) for n, d, nets, reqs in specs]
-    results, states, _ = _serve(specs, opts, [_interleaved(specs, 2)], max_inflight=2)
+    results, states, _ = _serve(specs, opts, [_interleaved(specs, 2)], max_inflight=2, order=order)
     for (i, r), res in sorted(results.items()):
         assert res["status"] == Q.QTASK_OK
         assert res["state_hash"] == alone[i][0][r], "session %d request %d" % (i, r)
     for i in range(len(specs)):
         assert bytes_equal(states[i], alone[i][1])
+
 
 
 def test_admission_evicts_and_restores():

@@ -517,6 +517,7 @@ def test_server_opts_and_edit_records():
     o = Q.qtask_server_opts_default()
     assert o.struct_size == Q.ctypes.sizeof(Q.qtask_server_opts)
     assert o.budget_bytes == 256 << 30 and o.small_qubits == 16 and o.max_inflight >= 1 and o.use_graph == 1
+    assert o.order == 0
     ins = W.Edit(op="insert", net=3, gate=("cp", (1, 4), (0.5,)), new_net=True)
     recs = Q.make_edits(ins)
     assert [r.op for r in recs] == [2, 0]
