@@ -2,7 +2,7 @@
 // QTASK_FUSE_AUTO, the fusion mode and width k.
 //
 // The paper leaves the block size to the user because the best value depends
-// on the circuit and the machine (Section IV-F).  Here the library measures
+// on the circuit and the machine (Section IV-E).  Here the library measures
 // instead: at the first update of a session it plans the circuit's first
 // levels with every candidate, runs each plan on the device (twice, keeping
 // the second timing, unless the first is already well behind), times the

@@ -261,3 +261,110 @@ def test_worked_example_paper_ranges_cover_exact_blocks():
         if name.endswith("_first"):
             exact = {b for b in exact if b <= ranges[0][1]}
         assert exact <= hull, name
+
+
+# ------------------------------------------- reductions and helper functions
+# The state is a unit vector of 2^n amplitudes (Section II-A); the helpers
+# below are the plain definitions the parity tests lean on: the squared norm,
+# the inner product <a|b> (conjugate-linear in its first argument), fidelity
+# |<a|b>|^2 / (<a|a><b|b>), per-net snapshots and changed-block sets.
+
+KET0 = np.array([1, 0], dtype=complex)
+KET1 = np.array([0, 1], dtype=complex)
+PLUS = np.array([1, 1], dtype=complex) / math.sqrt(2)
+MINUS = np.array([1, -1], dtype=complex) / math.sqrt(2)
+
+
+def _rand_state(rng, n):
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / math.sqrt(sum(abs(complex(z)) ** 2 for z in v))
+
+
+def test_norm2_closed_forms():
+    # amplitudes k + i k: sum of 2 k^2 over k < 2^n is (2^n - 1) 2^n (2^(n+1) - 1) / 3
+    for n in (1, 3, 6):
+        k = np.arange(1 << n, dtype=float)
+        want = (2 ** n - 1) * 2 ** n * (2 ** (n + 1) - 1) / 3
+        assert oracle.norm2(k + 1j * k) == want
+    assert oracle.norm2(PLUS) == pytest.approx(1.0, abs=4e-16)
+    # complex64 input is widened before squaring
+    assert oracle.norm2(np.array([3 + 4j], dtype=np.complex64)) == 25.0
+
+
+def test_inner_conjugates_its_first_argument():
+    rng = np.random.default_rng(31)
+    psi = _rand_state(rng, 5)
+    n2 = oracle.norm2(psi)
+    # <psi|i psi> = i <psi|psi> and <i psi|psi> = -i <psi|psi>: fixes which side is conjugated
+    assert abs(oracle.inner(psi, 1j * psi) - 1j * n2) < 1e-15
+    assert abs(oracle.inner(1j * psi, psi) + 1j * n2) < 1e-15
+    # textbook values on one qubit
+    assert abs(oracle.inner(KET0, PLUS) - 2 ** -0.5) < 3e-16
+    assert abs(oracle.inner(PLUS, MINUS)) < 1e-16
+    assert abs(oracle.inner(KET1, MINUS) + 2 ** -0.5) < 3e-16
+    # <0|(a|0> + b|1>)> picks a; as a bra, a|0> + b|1> gives conj(b) against |1>
+    a, b = 0.6 + 0.2j, -0.3 + 0.7j
+    assert oracle.inner(KET0, a * KET0 + b * KET1) == a
+    assert oracle.inner(a * KET0 + b * KET1, KET1) == b.conjugate()
+    assert oracle.inner(a * KET0, KET0) == a.conjugate()
+
+
+def test_inner_against_python_sum_and_symmetry():
+    rng = np.random.default_rng(32)
+    for n in (1, 2, 4):
+        x, y = _rand_state(rng, n), _rand_state(rng, n)
+        want = sum(complex(p).conjugate() * complex(q) for p, q in zip(x, y))
+        assert abs(oracle.inner(x, y) - want) < 1e-15
+        assert abs(oracle.inner(y, x) - want.conjugate()) < 1e-15
+        # linear in the second argument, index by index (a transposed or
+        # reversed operand would break this)
+        e = np.zeros(1 << n, dtype=complex)
+        for k in range(1 << n):
+            e[:] = 0
+            e[k] = 1
+            assert oracle.inner(e, y) == complex(y[k])
+
+
+def test_fidelity_closed_forms():
+    rng = np.random.default_rng(33)
+    psi = _rand_state(rng, 4)
+    for phi in (0.0, 0.7, math.pi, 4.0):
+        assert oracle.fidelity(psi, np.exp(1j * phi) * psi) == pytest.approx(1.0, abs=1e-15)
+    assert oracle.fidelity(KET0, KET1) == 0.0
+    assert oracle.fidelity(KET0, PLUS) == pytest.approx(0.5, abs=1e-16)   # a missing square would give 2^-1/2
+    assert oracle.fidelity(PLUS, MINUS) == pytest.approx(0.0, abs=1e-32)
+    for th in (0.1, 0.9, 1.3):
+        v = math.cos(th) * KET0 + math.sin(th) * KET1
+        assert oracle.fidelity(KET0, v) == pytest.approx(math.cos(th) ** 2, abs=1e-16)
+    # invariant under rescaling either argument (the norms are divided out)
+    phi = _rand_state(rng, 4)
+    f = oracle.fidelity(psi, phi)
+    assert 0.0 < f < 1.0
+    assert oracle.fidelity(3.0 * psi, phi) == pytest.approx(f, rel=1e-14)
+    assert oracle.fidelity(psi, (0.25 - 2j) * phi) == pytest.approx(f, rel=1e-14)
+    assert oracle.fidelity(phi, psi) == pytest.approx(f, rel=1e-14)
+
+
+def test_snapshots_step_by_brute_force():
+    rng = np.random.default_rng(34)
+    for n in (1, 3, 5):
+        nets = _random_circuit(rng, n, 5)
+        snaps = oracle.snapshots(n, nets)
+        assert len(snaps) == len(nets) + 1
+        e0 = np.zeros(1 << n, dtype=complex)
+        e0[0] = 1
+        assert np.array_equal(snaps[0], e0)
+        for i, net in enumerate(nets):
+            np.testing.assert_allclose(snaps[i + 1], bruteforce.net_matrix(n, net) @ snaps[i], atol=1e-14)
+        np.testing.assert_array_equal(snaps[-1], oracle.simulate(n, nets))
+
+
+def test_changed_blocks_by_hand():
+    a = np.zeros(16, dtype=complex)
+    b = a.copy()
+    b[5] = 1e-300      # block 1 of 4-amplitude blocks
+    b[15] = -0.0 + 1j  # block 3
+    assert oracle.changed_blocks(a, b, 2) == {1, 3}
+    assert oracle.changed_blocks(a, b, 0) == {5, 15}
+    assert oracle.changed_blocks(a, b, 4) == {0}
+    assert oracle.changed_blocks(a, a.copy(), 1) == set()
