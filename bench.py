@@ -1,21 +1,24 @@
-"""Benchmark: full simulation and incremental update of a 24-qubit layered
-random circuit (200 levels of RX/RY/RZ on every qubit + a random CNOT
-matching; 100 batches of 1-4 random gate inserts/removals at uniform levels).
+"""Benchmark, headline: configuration 5 -- a 32-qubit complex128 state
+(64 GiB) under a 500-level controlled-phase ladder circuit (RX/RY/RZ on every
+qubit, then CP on even and on odd adjacent pairs), with checkpoints every 50
+levels (three stored, as many as fit beside the state in 288 GB).
 
-A step = one modifier batch: apply the edits, run the incremental update
-(timed), then a full re-simulation of the modified circuit (timed) whose
-bytes must equal the incremental result.  ``value`` is the full simulation's
-achieved HBM throughput (algorithmic bytes / wall time of the full
-re-simulations).  The JSON line also carries the incremental p50/p99 latency
-and speedup, the complex64 tier, the pass kernel's roofline, and these
-legs (each can be switched off):
-  * append protocol: the same circuit built net by net with an update after
-    each, compared with full re-simulations at the same depth;
-  * large state: the layered family at 28 qubits (4 GiB, far above the
-    Infinity Cache) for an HBM-only figure;
-  * serving: 256 sessions of 12-28 qubits with Poisson modify+update
-    requests, both precisions;
-  * cpu baseline: the CPU oracle on a bounded sample, all threads and one.
+A step = one single-gate insert at a uniformly random level (alternately a
+gate inside one tile and a gate across tiles) and its incremental update.
+``value`` is the HBM throughput of the timed steps (algorithmic bytes of
+their pass launches / wall time of the steps); ``roofline`` is the pass
+kernel's bytes per launch over its average launch time.  After the timed
+steps a full re-simulation checks the result bitwise, and two more edits are
+each compared with their own full re-simulation (speedup p50 against the
+replay bound of uniform edits).
+
+Also in the line (each can be switched off): the 10-qubit launch-latency
+circuit, the 24-qubit layered configuration in complex128 and complex64
+(cache-assisted), the serving curve (256 sessions, two Poisson loads and a
+saturating burst, both precisions) and the CPU oracle on a bounded sample of
+the headline workload with its max-abs against the device.  ``--extras``
+runs the 28-qubit state, the paper's other incremental protocols and the
+30-qubit fused-unitary configuration instead.
 """
 import argparse
 import json
@@ -52,10 +55,10 @@ def fidelity(a, b):
 def run_tier(Q, W, wl, dtype, steps, warmup, shape=None):
     nets = [list(x) for x in wl.nets]
     if shape:  # a pinned tile shape (b, c) instead of the autotuner's pick
-        sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=0,
+        sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_nets, autotune=0,
                           tile_bits=shape[0], low_bits=shape[1])
     else:
-        sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=1)
+        sim = Q.Simulator(wl.n, dtype, device=0, ckpt_interval=wl.ckpt_nets, autotune=1)
     sim.build(nets)
     t0 = time.perf_counter()
     st = sim.update()          # first update: autotune + full simulation
@@ -194,28 +197,87 @@ def run_serving(Q, W, dtype, specs, keep_n=20, order=0):
         Q.qtask_server_destroy(sv)
 
 
-def run_serving_sweep(Q, W, dtype, rates, seed=4242):
-    """Latency against offered load: one request (1-3 edits) per session,
-    arriving as one Poisson stream of the given aggregate rate (requests/s)
-    spread over the sessions in a random order."""
+def run_serving_curve(Q, W, dtype, rates, per_phase=128, keep_n=20, seed=4242):
+    """Latency against offered load on one server: the 256 sessions are
+    opened and simulated once (untimed), then each phase submits requests of
+    1-3 edits as one Poisson stream at the offered rate (requests/s) over
+    `per_phase` sessions in random order, and a last phase submits one
+    request to every session at once (the saturation point).  Each phase is
+    drained before the next; a request's latency is submit to done."""
+    import threading
+
     import numpy as np
 
-    base = W.serving_sessions(requests=1)
-    curve = []
-    for rate in rates:
-        rng = np.random.default_rng(seed)
-        times = np.cumsum(rng.exponential(1.0 / rate, size=len(base)))
-        order = rng.permutation(len(base))
-        for k, i in enumerate(order):
-            base[i].arrivals = [float(times[k])]
-        res, _ = run_serving(Q, W, dtype, base, keep_n=0)
-        point = {"offered_per_s": rate, "served_per_s": res["updates_per_s"], "latency_ms_p50": res["latency_ms_p50"],
-                 "latency_ms_p99": res["latency_ms_p99"], "service_ms_p50": res["service_ms_p50"],
-                 "failed": res["failed"], "requests": res["requests"]}
-        log("serving sweep %s offered %.0f/s: served %.1f/s, p50 %.0f ms, p99 %.0f ms" % (
-            dtype, rate, point["served_per_s"], point["latency_ms_p50"], point["latency_ms_p99"]))
-        curve.append(point)
-    return curve
+    dt = Q.QTASK_C128 if dtype == "c128" else Q.QTASK_C64
+    specs = W.serving_sessions(requests=len(rates) + 1)
+    budget = Q.qtask_server_opts_default().budget_bytes
+    sv = Q.qtask_server_create(Q.qtask_server_opts_default())
+    rng = np.random.default_rng(seed)
+    try:
+        t0 = time.perf_counter()
+        sids = [Q.qtask_server_open(sv, sp.n, dt, Q.qtask_opts_default(device=0), sp.nets) for sp in specs]
+        warm = [Q.qtask_server_submit(sv, sid, []) for sid in sids]
+        Q.qtask_server_drain(sv)
+        bad = sum(Q.qtask_server_wait(sv, t, 0.0)["status"] != Q.QTASK_OK for t in warm)
+        log("serving %s: 256 sessions opened and simulated in %.1f s" % (dtype, time.perf_counter() - t0))
+        nreq = [0] * len(specs)  # requests used per session
+        curve = []
+        for ph, rate in enumerate(list(rates) + [None]):
+            if rate is None:
+                order = list(range(len(specs)))
+                times = [0.0] * len(order)
+            else:
+                order = [int(i) for i in rng.permutation(len(specs))[:per_phase]]
+                times = list(np.cumsum(rng.exponential(1.0 / rate, size=len(order))))
+            recs = []
+            for i in order:
+                recs.append([c for e in specs[i].requests[nreq[i]] for c in Q.make_edits(e)])
+                nreq[i] += 1
+            tickets = []
+
+            def feed():
+                start = time.perf_counter()
+                for k, i in enumerate(order):
+                    d = times[k] - (time.perf_counter() - start)
+                    if d > 0:
+                        time.sleep(d)
+                    tickets.append(Q.qtask_server_submit(sv, sids[i], recs[k]))
+
+            t0 = time.perf_counter()
+            th = threading.Thread(target=feed)
+            th.start()
+            th.join()
+            Q.qtask_server_drain(sv)
+            wall = time.perf_counter() - t0
+            res = [Q.qtask_server_wait(sv, t, 0.0) for t in tickets]
+            bad += sum(r["status"] != Q.QTASK_OK for r in res)
+            lat = [r["latency_ms"] for r in res]
+            svc = [r["done_ms"] - r["start_ms"] for r in res]
+            point = {"offered_per_s": rate if rate is not None else "all at once", "requests": len(res),
+                     "served_per_s": len(res) / wall, "latency_ms_p50": pct(lat, 50),
+                     "latency_ms_p99": pct(lat, 99), "service_ms_p50": pct(svc, 50)}
+            log("serving %s offered %s: served %.1f/s, p50 %.0f ms, p99 %.0f ms" % (
+                dtype, point["offered_per_s"], point["served_per_s"], point["latency_ms_p50"],
+                point["latency_ms_p99"]))
+            curve.append(point)
+        used, resident = Q.qtask_server_usage(sv)
+        peak = Q.qtask_server_peak_bytes(sv)
+        kept = {}
+        for i, sid in enumerate(sids):
+            if specs[i].n <= keep_n:
+                h = Q.qtask_server_session(sv, sid)
+                try:
+                    kept[i] = Q.qtask_read_amplitudes(h, 0, 1 << specs[i].n, dt)
+                except Q.QtaskError as e:
+                    if e.code != Q.QTASK_E_STALE:  # evicted sessions hold no state
+                        raise
+        sat = curve[-1]
+        return {"dtype": dtype, "sessions": len(sids), "failed": bad, "curve": curve,
+                "updates_per_s": sat["served_per_s"], "latency_ms_p50": sat["latency_ms_p50"],
+                "latency_ms_p99": sat["latency_ms_p99"], "budget_bytes": budget, "peak_bytes": peak,
+                "device_bytes": used, "resident": resident}, kept
+    finally:
+        Q.qtask_server_destroy(sv)
 
 
 def run_append(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10):
@@ -254,7 +316,7 @@ def run_small(Q, W, repeats=20):
     re-simulation of the same circuit, compared by hash."""
     wl = W.config(1)
     nets = [list(x) for x in wl.nets]
-    first, inc, full, mismatches = [], [], [], 0
+    first, inc, full, plan, modes, mismatches = [], [], [], [], [], 0
     for _ in range(repeats):
         s = Q.Simulator(wl.n, "c128", device=0, ckpt_interval=5)
         try:
@@ -272,7 +334,10 @@ def run_small(Q, W, repeats=20):
                 for e in batch:
                     W.apply_edit(work, e)
                     s.apply_edit(e)
-                inc.append(s.update()["wall_ms"])
+                st = s.update()
+                inc.append(st["wall_ms"])
+                plan.append(st["plan_ms"])
+                modes.append(st["mode"])
                 h = s.hash()
                 full.append(s.update(full=True)["wall_ms"])
                 mismatches += int(s.hash() != h)
@@ -287,7 +352,9 @@ def run_small(Q, W, repeats=20):
     return {"workload": "dense random circuit, 10 qubits, 20 levels, 10 single-gate modifiers; complex128",
             "first_update_us_p50": 1e3 * pct(first, 50),
             "update_us_p50": 1e3 * pct(inc, 50), "update_us_p99": 1e3 * pct(inc, 99),
-            "full_us_p50": 1e3 * pct(full, 50), "updates": len(inc), "mismatches": mismatches}
+            "full_us_p50": 1e3 * pct(full, 50), "update_plan_us_p50": 1e3 * pct(plan, 50),
+            "update_modes": {str(m): modes.count(m) for m in sorted(set(modes))},
+            "updates": len(inc), "mismatches": mismatches}
 
 
 def run_protocols(Q, wl, dtype, tile_bits, low_bits, every=25, ckpt_nets=10, mixes=50, seed=77):
@@ -370,7 +437,7 @@ def run_large(Q, W, n=28, levels=100, dtype="c128"):
     """Full simulations of the layered family at a state far larger than the
     256 MB Infinity Cache: HBM-only throughput of the pass kernel."""
     wl = W.config(2, n=n, levels=levels, batches=1)
-    s = Q.Simulator(n, dtype, device=0, ckpt_interval=wl.ckpt_levels, autotune=1)
+    s = Q.Simulator(n, dtype, device=0, ckpt_interval=wl.ckpt_nets, autotune=1)
     try:
         s.build(wl.nets)
         s.update()
@@ -388,44 +455,112 @@ def run_large(Q, W, n=28, levels=100, dtype="c128"):
             "tile_bits": o.tile_bits, "low_bits": o.low_bits}
 
 
-def run_ladder32(Q, W, levels=60, edits=6, tile_bits=12, low_bits=3, ckpt_nets=45):
-    """Configuration 5 at reduced depth: 32 qubits in complex128 (a 64 GiB
-    state plus two 64 GiB checkpoints), rotations and controlled-phase
-    ladders, then single-gate inserts alternating between gates inside one
-    tile (all qubits below b) and gates with a qubit at or above b.  Each
-    update is timed, then a full re-simulation of the same circuit, and the
-    two states are compared by hash."""
-    n = 32
+HEADLINE = dict(n=32, levels=500, ckpt_nets=150, max_ckpts=3, tile_bits=12, low_bits=5)
+
+
+def run_headline(Q, W, steps, warmup, tile_bits=None, low_bits=None, levels=None, verify_edits=2):
+    """Configuration 5, the headline: 32 qubits in complex128 (a 64 GiB state
+    and three 64 GiB checkpoints, one per 50-level segment boundary that
+    fits: levels 125, 250 and 375 of 500), 500 levels of RX/RY/RZ on every
+    qubit plus controlled-phase ladders on even and odd adjacent pairs.
+
+    After the first (full) simulation, `warmup` untimed steps insert a gate
+    in the circuit's last segment; then `steps` timed steps each insert one
+    gate at a uniformly random net, alternating between gates whose qubits
+    all lie below the tile bits (inside one tile) and gates with a qubit at
+    or above them, and run the incremental update.  A full re-simulation
+    then checks the result bitwise (state hash), and `verify_edits` more
+    edits (one inside a tile, one across) are each timed as an update and
+    compared with their own full re-simulation."""
+    n = HEADLINE["n"]
+    levels = levels or HEADLINE["levels"]
+    b = tile_bits or HEADLINE["tile_bits"]
+    c = low_bits or HEADLINE["low_bits"]
+    K = HEADLINE["ckpt_nets"]
     wl = W.config(5, levels=levels, batches=1)
     nets = [list(x) for x in wl.nets]
-    batches = W.split_edits(n, nets, 5005, edits, tile_bits)
-    s = Q.Simulator(n, "c128", device=0, ckpt_interval=ckpt_nets, max_ckpts=2, tile_bits=tile_bits,
-                    low_bits=low_bits)
+    sim = Q.Simulator(n, "c128", device=0, ckpt_interval=K, max_ckpts=HEADLINE["max_ckpts"], tile_bits=b,
+                      low_bits=c, relabel=1, autotune=0)
+    rows = []
     try:
-        s.build(nets)
-        st = s.update()
-        full0 = st
-        rows = []
-        for i, batch in enumerate(batches):
+        sim.build(nets)
+        t0 = time.perf_counter()
+        first = sim.update()
+        log("headline: 32-qubit ladder, %d levels (%d nets): first full simulation %.0f ms (%d passes, "
+            "plan %.0f ms, wall %.1f s)" % (levels, len(nets), first["kernel_ms"], first["passes"], first["plan_ms"],
+                                           time.perf_counter() - t0))
+        for i, batch in enumerate(W.split_edits(n, nets, 5004, warmup, b, tail=K)):
             for e in batch:
                 W.apply_edit(nets, e)
-                s.apply_edit(e)
-            st = s.update()
-            h = s.hash()
-            sf = s.update(full=True)
+                sim.apply_edit(e)
+            st = sim.update()
+            log("headline warm-up %d: %.0f ms from net %d" % (i, st["wall_ms"], st["first_level"]))
+        timed = W.split_edits(n, nets, 5005, steps, b)
+        t0 = time.perf_counter()
+        for i, batch in enumerate(timed):
+            for e in batch:
+                W.apply_edit(nets, e)
+                sim.apply_edit(e)
+            st = sim.update()
             rows.append({"high": i % 2 == 1, "gate": batch[0].gate[0], "qubits": list(batch[0].gate[1]),
-                         "mode": st["mode"], "first_level": st["first_level"], "inc_ms": st["kernel_ms"],
-                         "full_ms": sf["kernel_ms"], "equal": h == s.hash()})
-            log("ladder-32 edit %d (%s on %s): mode %d from net %d, %.0f ms vs full %.0f ms" % (
-                i, batch[0].gate[0], batch[0].gate[1], st["mode"], st["first_level"], st["kernel_ms"], sf["kernel_ms"]))
+                         "mode": st["mode"], "first_level": st["first_level"], "wall_ms": st["wall_ms"],
+                         "kernel_ms": st["kernel_ms"], "plan_ms": st["plan_ms"], "bytes": st["bytes"],
+                         "passes": st["passes"], "levels_replayed": st["levels_replayed"],
+                         "levels_total": st["levels_total"], "gate_amp_updates": st["gate_amp_updates"]})
+            log("headline step %d (%s on %s): mode %d from net %d, %.0f ms, %d passes" % (
+                i, batch[0].gate[0], batch[0].gate[1], st["mode"], st["first_level"], st["wall_ms"], st["passes"]))
+        timed_s = time.perf_counter() - t0
+        # the timed steps' result against a full re-simulation, bitwise
+        h_inc = sim.hash()
+        full = sim.update(full=True)
+        mismatches = int(sim.hash() != h_inc)
+        fulls = [full]
+        verify = []
+        for i, batch in enumerate(W.split_edits(n, nets, 5006, verify_edits, b)):
+            for e in batch:
+                W.apply_edit(nets, e)
+                sim.apply_edit(e)
+            si = sim.update()
+            h = sim.hash()
+            sf = sim.update(full=True)
+            fulls.append(sf)
+            eq = h == sim.hash()
+            mismatches += int(not eq)
+            verify.append({"high": i % 2 == 1, "gate": batch[0].gate[0], "qubits": list(batch[0].gate[1]),
+                           "mode": si["mode"], "first_level": si["first_level"], "inc_ms": si["wall_ms"],
+                           "full_ms": sf["wall_ms"], "speedup": sf["wall_ms"] / si["wall_ms"], "equal": eq})
+            log("headline check %d (%s on %s): update %.0f ms from net %d, full %.0f ms, equal %s" % (
+                i, batch[0].gate[0], batch[0].gate[1], si["wall_ms"], si["first_level"], sf["wall_ms"], eq))
+        o = Q.qtask_get_opts(sim.h)
     finally:
-        s.close()
-    gbs = full0["bytes"] / (full0["kernel_ms"] * 1e-3) / 1e9
-    sp = [r["full_ms"] / r["inc_ms"] for r in rows]
-    return {"qubits": n, "levels": levels, "nets": len(wl.nets), "dtype": "c128", "state_gib": 64,
-            "tile_bits": tile_bits, "low_bits": low_bits, "ckpt_nets": ckpt_nets,
-            "full_ms": full0["kernel_ms"], "passes": full0["passes"], "gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
-            "edits": rows, "speedup_p50": pct(sp, 50), "mismatches": sum(not r["equal"] for r in rows)}
+        sim.close()
+    full_ms = pct([f["wall_ms"] for f in fulls], 50)
+    inc = [r["wall_ms"] for r in rows]
+    byt = sum(r["bytes"] for r in rows)
+    kms = sum(r["kernel_ms"] for r in rows)
+    launches = sum(r["passes"] for r in rows)
+    lo = [r for r in rows if not r["high"]]
+    hi = [r for r in rows if r["high"]]
+    return {
+        "qubits": n, "levels": levels, "nets": len(wl.nets), "dtype": "c128", "state_gib": 64,
+        "tile_bits": o.tile_bits, "low_bits": o.low_bits, "relabel": o.relabel,
+        "ckpt_levels": K // 3, "ckpts_stored": HEADLINE["max_ckpts"],
+        "first_full_ms": first["wall_ms"], "first_full_kernel_ms": first["kernel_ms"],
+        "full_passes": first["passes"], "full_bytes": first["bytes"],
+        "full_gbs": first["bytes"] / (first["kernel_ms"] * 1e-3) / 1e9,
+        "full_ms_p50": full_ms,
+        "timed_s": timed_s, "steps": rows,
+        "inc_ms_p50": pct(inc, 50), "inc_ms_p99": pct(inc, 99),
+        "inc_ms_p50_inside_tile": pct([r["wall_ms"] for r in lo], 50),
+        "inc_ms_p50_across_tiles": pct([r["wall_ms"] for r in hi], 50),
+        "speedup_p50": full_ms / pct(inc, 50), "speedup_p99": full_ms / pct(inc, 99),
+        "replay_bound_speedup_p50": pct([r["levels_total"] / max(r["levels_replayed"], 1) for r in rows], 50),
+        "timed_gbs": byt / (kms * 1e-3) / 1e9 if kms else None,
+        "timed_wall_gbs": byt / timed_s / 1e9,
+        "launches": launches, "launch_bytes": byt / max(launches, 1), "launch_ms": kms / max(launches, 1),
+        "gate_amp_updates_per_s": sum(r["gate_amp_updates"] for r in rows) / timed_s,
+        "verify": verify, "mismatches": mismatches,
+    }
 
 
 MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # dense FP32 / FP64 matrix-core peaks
@@ -485,33 +620,58 @@ def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 <<
     return out
 
 
-def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=150):
-    """Time the CPU oracle (all host threads) on the first nets of the same
-    circuit, adding nets until about min_s seconds of work."""
+def cpu_baseline(Q, W, full_bytes_per_gate, min_s=10.0):
+    """The CPU oracle (all host threads, then one) on a bounded sample of the
+    headline workload: the 32-qubit circuit's first gates, one at a time,
+    until about min_s seconds of work (the oracle holds the whole 64 GiB
+    state in host memory; its pages are touched before the timing).  The
+    same gates then run on the device and the two states are compared on
+    the first 2^20 amplitudes and 4096 spread over the rest."""
+    import numpy as np
+
     from oracle import oracle
 
+    n = HEADLINE["n"]
+    wl = W.config(5, levels=1, batches=1)
+    gates = [g for net in wl.nets for g in net]
     threads = oracle.max_threads()
-    psi = oracle.basis(wl.n)
-    gates = 0
+    t0 = time.perf_counter()
+    psi = np.empty(1 << n, dtype=np.complex128)
+    psi.fill(0)
+    psi[0] = 1
+    touch_s = time.perf_counter() - t0
     used = 0
     t0 = time.perf_counter()
-    for net in wl.nets[:max_nets]:
-        oracle.apply_gates(wl.n, psi, list(net), threads)
-        gates += len(net)
+    for g in gates:
+        oracle.apply_gates(n, psi, [g], threads)
         used += 1
         if time.perf_counter() - t0 >= min_s:
             break
     dt = time.perf_counter() - t0
-    # the same oracle on one thread, over the first nets (about 3 s)
-    psi1 = oracle.basis(wl.n)
+    # the device on the same first `used` gates (they lie in the first net)
+    err = 0.0
+    idx = np.linspace(1 << 20, (1 << n) - 1, 4096).astype(np.int64)
+    s = Q.Simulator(n, "c128", device=0, tile_bits=HEADLINE["tile_bits"], low_bits=HEADLINE["low_bits"],
+                    relabel=1)
+    try:
+        s.build([gates[:used]])
+        s.update()
+        for lo in range(0, 1 << 20, 1 << 18):
+            err = max(err, float(np.max(np.abs(s.state(lo, 1 << 18) - psi[lo:lo + (1 << 18)]))))
+        for i in idx:
+            err = max(err, float(abs(s.state(int(i), 1)[0] - psi[int(i)])))
+    finally:
+        s.close()
+    # one thread, on the next gates (about min_s / 3)
     g1 = 0
     t1 = time.perf_counter()
-    for net in wl.nets[:max_nets]:
-        oracle.apply_gates(wl.n, psi1, list(net), 1)
-        g1 += len(net)
+    for g in gates[used:]:
         if time.perf_counter() - t1 >= min_s / 3:
             break
+        oracle.apply_gates(n, psi, [g], 1)
+        g1 += 1
     dt1 = time.perf_counter() - t1
+    del psi
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -519,34 +679,74 @@ def cpu_baseline(W, wl, full_bytes_per_gate, min_s=10.0, max_nets=150):
     except OSError:
         pass
     return {
-        "value": full_bytes_per_gate * gates / dt / 1e9,
+        "value": full_bytes_per_gate * used / dt / 1e9,
         "unit": "GB/s",
         "cores": threads,
         "cpu_model": model,
         "host_cpus": os.cpu_count(),
         "kind": "oracle",
-        "sample": "first %d nets (%d gates) of the %d-qubit circuit, complex128, %.1f s on %d threads; value = the "
-                  "GPU plan's bytes for the same gates / oracle time" % (used, gates, wl.n, dt, threads),
-        "gate_amp_updates_per_s": gates * (1 << wl.n) / dt,
-        "full_sim_s_extrapolated": dt * W.count_gates(wl.nets) / gates,
-        "value_1_thread": full_bytes_per_gate * g1 / dt1 / 1e9,
-        "gate_amp_updates_per_s_1_thread": g1 * (1 << wl.n) / dt1,
+        "sample": "the first %d gates of the 32-qubit, 500-level ladder circuit (complex128, the whole 64 GiB state "
+                  "in host memory), %.1f s on %d threads; value = the device plan's bytes per gate (full "
+                  "simulation average) times the gates, divided by the oracle time" % (used, dt, threads),
+        "gate_amp_updates_per_s": used * float(1 << n) / dt,
+        "value_1_thread": full_bytes_per_gate * g1 / dt1 / 1e9 if g1 else None,
+        "gate_amp_updates_per_s_1_thread": g1 * float(1 << n) / dt1 if g1 else None,
+        "first_touch_s": touch_s,
+        "max_abs_device_c128_vs_oracle": err,
+        "compared": "first 2^20 amplitudes and 4096 spread over the rest, after the sampled gates",
     }
+
+
+def load_traffic(path):
+    """HBM bytes per launch from a committed counter summary, or None once the
+    kernel source no longer matches the one the counters were taken on."""
+    if not path or not os.path.exists(path):
+        return None
+    from paper_2210_01076_amd import profiling
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != profiling.kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_extras(Q, W, args):
+    """The legs that do not fit the default run's time: the paper's other
+    incremental protocols on the 24-qubit circuit, the 28-qubit layered
+    state, and the 30-qubit fused-unitary configuration."""
+    wl = W.config(2)
+    out = {"metric": "extra legs (see each entry)"}
+    out["large_state"] = run_large(Q, W)
+    log("28-qubit complex128 full simulation: %.1f ms, %.0f GB/s" % (out["large_state"]["full_ms"],
+                                                                   out["large_state"]["gbs"]))
+    sim, _, r = run_tier(Q, W, wl, "c128", 2, 0)
+    sim.close()
+    out["append_protocol"] = run_append(Q, wl, "c128", r["tile_bits"], r["low_bits"])
+    out["other_protocols"] = run_protocols(Q, wl, "c128", r["tile_bits"], r["low_bits"])
+    out["fused_dense"] = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels,
+                                   tuned=not args.no_fused_tuned)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-tier24", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-append", action="store_true")
-    ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--no-fused", action="store_true")
-    ap.add_argument("--ladder32", action="store_true",
-                    help="only the 32-qubit controlled-phase ladder with single-gate edits (about a minute)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 32-qubit headline (profiling runs)")
+    ap.add_argument("--headline-levels", type=int, default=0,
+                    help="depth of the headline circuit (default 500; profiling runs may shorten it)")
+    ap.add_argument("--verify-edits", type=int, default=2,
+                    help="headline edits after the timed steps that are each compared with a full re-simulation")
+    ap.add_argument("--tile-bits", type=int, default=0, help="headline tile bits (default 12)")
+    ap.add_argument("--low-bits", type=int, default=0, help="headline contiguous low bits (default 5)")
+    ap.add_argument("--extras", action="store_true",
+                    help="instead of the default run: the 28-qubit state, the paper's other incremental "
+                         "protocols and the 30-qubit fused-unitary legs, printed as one JSON line")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only the serving latency-throughput sweep (several minutes), printed as one JSON line")
     ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
@@ -554,14 +754,7 @@ def main():
     ap.add_argument("--no-fused-tuned", action="store_true",
                     help="skip the autotuned comparison run of the fused-unitary leg (its timing candidates "
                          "would mix into a profile of the fused kernels)")
-    ap.add_argument("--tile-bits", type=int, default=0,
-                    help="pin the complex128 tier's tile bits instead of autotuning (profiling runs: counter "
-                         "collection slows kernels and would sway the tuner's timings)")
-    ap.add_argument("--low-bits", type=int, default=3, help="contiguous low bits with --tile-bits")
-    ap.add_argument("--c64-tile-bits", type=int, default=0, help="the same for the complex64 tier")
-    ap.add_argument("--c64-low-bits", type=int, default=4, help="contiguous low bits with --c64-tile-bits")
-    ap.add_argument("--traffic-c64", default=os.path.join(ROOT, "profiles", "traffic_layered_n24_c64.json"))
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_layered_n24.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_ladder_n32.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the state and the serving sessions are not sharded across GPUs "
@@ -571,11 +764,9 @@ def main():
     from paper_2210_01076_amd import qtask as Q
     from paper_2210_01076_amd import workloads as W
 
-    if args.ladder32:
-        print(json.dumps({"metric": "32-qubit full simulation GB/s; single-gate update vs full re-simulation",
-                          "ladder32": run_ladder32(Q, W)}))
+    if args.extras:
+        print(json.dumps(run_extras(Q, W, args)))
         return
-
     if args.serving_sweep:
         sweep = {"metric": "serving request latency against offered load", "unit": "ms",
                  "workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels, "
@@ -585,152 +776,106 @@ def main():
         print(json.dumps(sweep))
         return
 
+    t_start = time.perf_counter()
     copy_gbs = Q.qtask_copy_bandwidth(0, 1 << 30, 20)
     log("copy kernel ceiling %.1f GB/s" % copy_gbs)
-    wl = W.config(2)
-    shape = (args.tile_bits, args.low_bits) if args.tile_bits else None
-    sim128, nets, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup, shape)
-    r64 = None
-    if not args.no_c64:
-        shape64 = (args.c64_tile_bits, args.c64_low_bits) if args.c64_tile_bits else None
-        sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup, shape64)
-        import numpy as np
-        a = sim128.state()
-        b = sim64.state().astype(np.complex128)
-        r64["max_abs_vs_c128"] = float(np.max(np.abs(a - b)))
-        r64["fidelity_vs_c128"] = fidelity(a, b)
-        sim64.close()
-    sim128.close()
+    head = run_headline(Q, W, args.steps, args.warmup, args.tile_bits or None, args.low_bits or None,
+                        args.headline_levels or None, args.verify_edits)
+    log("headline: update p50 %.0f ms p99 %.0f ms, full %.0f ms, speedup p50 %.2f (bound %.2f), %.0f GB/s per "
+        "launch, mismatches %d (%.0f s so far)" % (
+            head["inc_ms_p50"], head["inc_ms_p99"], head["full_ms_p50"], head["speedup_p50"],
+            head["replay_bound_speedup_p50"], head["launch_bytes"] / head["launch_ms"] / 1e6, head["mismatches"],
+            time.perf_counter() - t_start))
 
-    # before the serving leg: autotuner picks are cached per (qubits, dtype,
-    # gate mix), and the serving sessions tune while other sessions run, so
-    # a 28-qubit pick made there would be timed under contention
-    small = run_small(Q, W)
-    log("10-qubit circuit: update p50 %.0f us p99 %.0f us, full re-simulation p50 %.0f us, mismatches %d" % (
-        small["update_us_p50"], small["update_us_p99"], small["full_us_p50"], small["mismatches"]))
-
-    large = None
-    if not args.no_large:
-        large = run_large(Q, W)
-        log("28-qubit complex128 full simulation: %.1f ms, %.0f GB/s (%.2f of peak)" % (
-            large["full_ms"], large["gbs"], large["frac_of_peak"]))
-
+    tier24 = None
+    small = None
     serving = None
-    if not args.no_serving:
-        import numpy as np
-        specs = W.serving_sessions()
-        s128, kept128 = run_serving(Q, W, "c128", specs)
-        s64, kept64 = run_serving(Q, W, "c64", specs)
-        errs = [float(np.max(np.abs(kept128[i] - kept64[i].astype(np.complex128)))) for i in kept128 if i in kept64]
-        s64["max_abs_vs_c128"] = max(errs) if errs else None
-        s64["compared_sessions"] = len(errs)
-        # the same streams with the expected-shortest request started first
-        sf = {}
-        for dt in ("c128", "c64"):
-            r, _ = run_serving(Q, W, dt, specs, keep_n=0, order=1)
-            sf[dt] = {k: r[k] for k in ("latency_ms_p50", "latency_ms_p99", "service_ms_p50", "updates_per_s",
-                                        "failed")}
-        serving = {"workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels, "
-                               "Poisson requests of 1-3 edits (4 per session); sessions under 16 qubits batched",
-                   "order": "oldest request first",
-                   "c128": s128, "c64": s64,
-                   "shortest_first": sf}
-        log("serving, expected-shortest first: c128 p50 %.1f ms p99 %.1f ms | c64 p50 %.1f ms p99 %.1f ms" % (
-            sf["c128"]["latency_ms_p50"], sf["c128"]["latency_ms_p99"],
-            sf["c64"]["latency_ms_p50"], sf["c64"]["latency_ms_p99"]))
-        log("serving c128 p50 %.1f ms p99 %.1f ms %.1f upd/s | c64 p50 %.1f ms p99 %.1f ms %.1f upd/s" % (
-            s128["latency_ms_p50"], s128["latency_ms_p99"], s128["updates_per_s"],
-            s64["latency_ms_p50"], s64["latency_ms_p99"], s64["updates_per_s"]))
+    cpu = None
+    if not args.headline_only:
+        small = run_small(Q, W)
+        log("10-qubit circuit: update p50 %.0f us p99 %.0f us, full re-simulation p50 %.0f us, mismatches %d" % (
+            small["update_us_p50"], small["update_us_p99"], small["full_us_p50"], small["mismatches"]))
+        if not args.no_tier24:
+            import numpy as np
+            wl = W.config(2)
+            sim128, _, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup)
+            sim64, _, r64 = run_tier(Q, W, wl, "c64", args.steps, args.warmup)
+            a = sim128.state()
+            b = sim64.state().astype(np.complex128)
+            r64["max_abs_vs_c128"] = float(np.max(np.abs(a - b)))
+            r64["fidelity_vs_c128"] = fidelity(a, b)
+            sim64.close()
+            sim128.close()
+            tier24 = {"workload": "layered random circuit, 24 qubits, 200 levels (RX/RY/RZ on every qubit + random "
+                                  "CNOT matching), modifier batches of 1-4 random gate inserts/removals; checkpoints "
+                                  "every 50 levels; cache-assisted (the 256 MiB state is about the size of the "
+                                  "Infinity Cache)",
+                      "batches": args.steps, "ckpt_levels": wl.ckpt_nets // 2, "c128": r128, "c64": r64}
+            log("24-qubit tier: c128 update p50 %.1f ms vs full %.1f ms; c64 %.1f ms vs %.1f ms" % (
+                r128["inc_ms_p50"], r128["full_ms_p50"], r64["inc_ms_p50"], r64["full_ms_p50"]))
+        if not args.no_serving:
+            import numpy as np
+            s128, kept128 = run_serving_curve(Q, W, "c128", [11, 20])
+            s64, kept64 = run_serving_curve(Q, W, "c64", [23, 41])
+            errs = [float(np.max(np.abs(kept128[i] - kept64[i].astype(np.complex128)))) for i in kept128
+                    if i in kept64]
+            s64["max_abs_vs_c128"] = max(errs) if errs else None
+            s64["compared_sessions"] = len(errs)
+            serving = {"workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels; "
+                                   "requests of 1-3 edits: Poisson streams at about 50% and 90% of the saturated "
+                                   "rate over 128 sessions each, then one request to every session at once; "
+                                   "sessions under 16 qubits batched",
+                       "c128": s128, "c64": s64}
+        if not args.no_cpu:
+            per_gate = head["full_bytes"] / W.count_gates(W.config(5, levels=head["levels"], batches=1).nets)
+            cpu = cpu_baseline(Q, W, per_gate)
+            log("cpu oracle: %.2f GB/s equivalent on %d threads; device vs oracle max-abs %.2e" % (
+                cpu["value"], cpu["cores"], cpu["max_abs_device_c128_vs_oracle"]))
 
-    append = None
-    if not args.no_append:
-        append = run_append(Q, wl, "c128", r128["tile_bits"], r128["low_bits"])
-        log("append protocol: update p50 %.2f ms, speedup vs full p50 %.1f (at full depth %.1f)" % (
-            append["update_ms_p50"], append["speedup_p50"], append["speedup_at_full_depth"]))
-    protocols = None
-    if not args.no_append:
-        protocols = run_protocols(Q, wl, "c128", r128["tile_bits"], r128["low_bits"])
-        for k in ("insert_random_order", "remove_until_empty", "mixed_50"):
-            p = protocols[k]
-            log("%s: %d steps, update p50 %.2f ms p99 %.2f ms, speedup vs full p50 %s, mismatches %d" % (
-                k, p["steps"], p["update_ms_p50"], p["update_ms_p99"],
-                "%.1f" % p["speedup_p50"] if p["speedup_p50"] else "-", p["mismatches"]))
-    fused = None
-    if not args.no_fused:
-        fused = run_fused(Q, W, n=args.fused_qubits, levels=args.fused_levels, tuned=not args.no_fused_tuned)
-        log("%d-qubit fused k=5: complex64 %.0f ms (%.1f TFLOP/s on the matrix cores), complex128 %.0f ms "
-            "(%.1f TFLOP/s); fidelity %.12f, sampled max-abs %.2e" % (
-                fused["qubits"], fused["c64"]["full_ms"], fused["c64"]["mfma_tflops"], fused["c128"]["full_ms"],
-                fused["c128"]["mfma_tflops"], fused["fidelity_c64_vs_c128"], fused["max_abs_c64_vs_c128_sampled"]))
-        if "autotuned_c64" in fused:
-            log("autotuned complex64 on the same circuit: %.0f ms (fusion %s)" % (
-                fused["autotuned_c64"]["full_ms"], fused["autotuned_c64"]["fusion"]))
-
-    per_gate = r128["pass_bytes"] * r128["passes_per_full"] / W.count_gates(nets)
-    cpu = None if args.no_cpu else cpu_baseline(W, wl, per_gate)
-
-    # HBM bytes per launch from the committed counter summary, dropped once
-    # the kernel source no longer matches the one the counters were taken on
-    def load_traffic(path):
-        if not os.path.exists(path):
-            return None
-        from paper_2210_01076_amd import profiling
-        with open(path) as f:
-            rec = json.load(f)
-        if rec.get("kernel_source_hash") != profiling.kernel_source_hash():
-            return None
-        return rec.get("hbm_bytes_per_launch")
-
-    traffic = load_traffic(args.traffic)
-    if r64 is not None:
-        # the complex64 pass kernel's HBM bytes per launch, from its own summary
-        r64["traffic"] = load_traffic(args.traffic_c64)
-    achieved = r128["launch_bytes"] / (r128["launch_ms"] * 1e-3) / 1e9
+    achieved = head["launch_bytes"] / (head["launch_ms"] * 1e-3) / 1e9
+    b = head["tile_bits"]
     line = {
         "metric": "full-sim HBM GB/s vs peak; incremental update p50/p99 latency and speedup vs full re-sim",
-        "value": round(r128["full_gbs"], 1),
+        "value": round(head["timed_wall_gbs"], 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r128["timed_s"] * 1e3 / args.steps, 3),
+        "ms_per_step": round(head["timed_s"] * 1e3 / max(args.steps, 1), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "layered random circuit, 24 qubits, 200 levels (RX/RY/RZ on every qubit + random "
-                               "CNOT matching), 100 batches of 1-4 random gate inserts/removals; complex128",
-                   "qubits": 24, "levels": 200, "batches": 100, "ckpt_levels": wl.ckpt_levels,
-                   "tile_bits": r128["tile_bits"], "low_bits": r128["low_bits"]},
-        "frac_of_peak": round(r128["full_gbs"] / HBM_PEAK_GBS, 4),
+        "config": {"workload": "controlled-phase ladder circuit, 32 qubits, %d levels (RX/RY/RZ on every qubit, "
+                               "then CP on even and on odd adjacent pairs); one step = one single-gate insert at a "
+                               "uniformly random level (alternately inside one tile and across tiles) and its "
+                               "incremental update; complex128, 64 GiB state, checkpoints every 50 levels, 3 "
+                               "stored" % head["levels"],
+                   "qubits": 32, "levels": head["levels"], "edits": args.steps, "ckpt_levels": head["ckpt_levels"],
+                   "ckpts_stored": head["ckpts_stored"], "tile_bits": b, "low_bits": head["low_bits"],
+                   "relabel": head["relabel"]},
+        "frac_of_peak": round(head["timed_wall_gbs"] / HBM_PEAK_GBS, 4),
         "copy_ceiling_gbs": round(copy_gbs, 1),
-        "frac_of_copy_ceiling": round(r128["full_gbs"] / copy_gbs, 4),
-        "full_ms_p50": r128["full_ms_p50"],
-        "incremental_ms_p50": r128["inc_ms_p50"],
-        "incremental_ms_p99": r128["inc_ms_p99"],
-        "incremental_speedup_p50": r128["speedup_p50"],
-        "replay_bound_speedup_p50": r128["speedup_bound_p50"],
-        "incremental_mismatches": r128["mismatches"],
-        "updates_per_s": {"c128": r128["updates_per_s"], "c64": r64["updates_per_s"] if r64 else None},
-        "gate_amp_updates_per_s": r128["gate_amp_updates_per_s"],
-        "passes_per_full_sim": r128["passes_per_full"],
-        "c64": r64,
+        "full_sim_gbs": round(head["full_gbs"], 1),
+        "full_ms_p50": head["full_ms_p50"],
+        "incremental_ms_p50": head["inc_ms_p50"],
+        "incremental_ms_p99": head["inc_ms_p99"],
+        "incremental_speedup_p50": head["speedup_p50"],
+        "replay_bound_speedup_p50": head["replay_bound_speedup_p50"],
+        "incremental_mismatches": head["mismatches"],
+        "headline": head,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "qk_pass<double, false>", "bytes_per_launch": r128["launch_bytes"],
-                     "avg_launch_ms": r128["launch_ms"], "launches_timed": r128["launches"],
-                     "block": 1 << (r128["tile_bits"] - 4),
-                     "scope": "every pass launch of the timed steps (incremental and full), complex128",
-                     "note": "cache-assisted: the 24-qubit complex128 state (256 MiB) is about the size of the "
-                             "256 MB Infinity Cache; large_state is the HBM-only figure (28 qubits, 4 GiB)"},
-        "append_protocol": append,
-        "other_protocols": protocols,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.traffic),
+                     "kernel": "qk_pass<double, false>", "bytes_per_launch": head["launch_bytes"],
+                     "avg_launch_ms": head["launch_ms"], "launches_timed": head["launches"],
+                     "block": 1 << (b - 4),
+                     "scope": "every pass launch of the timed steps (32 qubits, complex128)"},
+        "tier24": tier24,
         "small_circuit": small,
-        "large_state": large,
-        "fused_dense": fused,
         "serving": serving,
         "cpu_baseline": cpu,
+        "run_s": time.perf_counter() - t_start,
     }
     print(json.dumps(line))
 

@@ -108,6 +108,12 @@ typedef struct qtask_opts {
     void *(*alloc)(size_t bytes, void *ctx); /* device allocator; NULL = hipMalloc */
     void (*free)(void *ptr, void *ctx);
     void *alloc_ctx;
+    int32_t relabel;        /* qubit relabelling inside checkpoint segments: 1 on, 0 off, -1 (default) on for
+                               states of 26 or more qubits.  A pass may store its tile with the qubits
+                               permuted among the tile's positions, so that the qubits the next passes need
+                               sit in the contiguous low positions every tile holds (longer contiguous runs
+                               per access at the same number of passes); each segment starts and ends in
+                               the plain layout (qubit k at bit k), so checkpoints and queries see it */
 } qtask_opts;
 
 typedef struct qtask_s *qtask_t;
@@ -175,7 +181,16 @@ int qtask_num_gates(qtask_t h, uint64_t *out);
  * the first modified level and re-simulate from there, touching only the
  * affected blocks when that set is closed (Section III-E).  Blocking.  The
  * result is bitwise identical to qtask_update_state_full on the same
- * circuit and options. */
+ * circuit and options.
+ * Errors: the update first plans on the host, then allocates every device
+ * buffer it needs (plans, state, new checkpoints, scratch; through the
+ * allocator hooks of qtask_opts when set) before it changes any of them.
+ * QTASK_E_NOMEM (an allocation failed) and QTASK_E_ARG (a plan could not be
+ * built) therefore leave the previous result, its checkpoints and their
+ * validity as they were; the modifiers stay pending, so amplitude queries
+ * return QTASK_E_STALE until an update succeeds, and that update resumes
+ * from the same checkpoints.  QTASK_E_DEVICE leaves the state undefined and
+ * the next update re-simulates from |0...0>. */
 int qtask_update_state(qtask_t h);
 /* Re-simulate the whole circuit from |0...0>, ignoring checkpoints. */
 int qtask_update_state_full(qtask_t h);
@@ -200,7 +215,7 @@ int qtask_state_hash(qtask_t h, uint64_t *out);
 /* Device pointer and size in bytes of the current state (read-only use;
  * valid until the next update or destroy). */
 int qtask_state_device_ptr(qtask_t h, const void **ptr, uint64_t *bytes);
-/* Device bytes held by the session (state + checkpoints + plans). */
+/* Device bytes held by the session (state, checkpoints, plans and scratch). */
 int qtask_device_bytes(qtask_t h, uint64_t *out);
 /* The options in effect (after defaults and autotuning). */
 int qtask_get_opts(qtask_t h, qtask_opts *out);
@@ -230,7 +245,9 @@ typedef struct qtask_server_s *qtask_server_t;
 typedef struct qtask_server_opts {
     uint32_t struct_size;
     int32_t device;
-    uint64_t budget_bytes;    /* device bytes the server may hold (state + checkpoints) */
+    uint64_t budget_bytes;    /* device bytes the sessions may hold together: state, checkpoints, plans and
+                                 per-session scratch (the server's own tables and the transient buffers of
+                                 a first-update autotune are not charged) */
     int32_t max_inflight;     /* large sessions updating at once */
     int32_t small_qubits;     /* sessions with n < small_qubits go through the batched graph launch (default 16) */
     int32_t use_graph;        /* 1 (default): capture the batched launch in a HIP graph */
@@ -275,7 +292,14 @@ int qtask_server_open(qtask_server_t s, int n_qubits, qtask_dtype dtype, const q
                       uint64_t n_levels, uint64_t n_gates, const int32_t *kinds,
                       const int32_t *qubits, const int32_t *nq, const double *params,
                       const uint64_t *level_of_gate, int32_t *session_out);
-/* Queue a request: apply the edits, then update the state.  Returns at once. */
+/* Queue a request: apply the edits, then update the state.  Returns at once.
+ * A request is admitted by the bytes its session holds after the update
+ * (edits that add levels can add checkpoints), evicting idle sessions
+ * least recently used first; it waits while that does not fit.  A request
+ * is all or nothing: when an edit fails, or the update fails with anything
+ * but QTASK_E_DEVICE (including QTASK_E_NOMEM for a session that can never
+ * fit the budget), its edits are undone and the session keeps its previous
+ * state. */
 int qtask_server_submit(qtask_server_t s, int32_t session, const qtask_edit *edits, int n_edits,
                         uint64_t *ticket_out);
 /* Block until the ticket's request finished (timeout_ms < 0: no limit). */
@@ -289,6 +313,9 @@ int qtask_server_drain(qtask_server_t s);
 int qtask_server_session(qtask_server_t s, int32_t session, qtask_t *out);
 /* Device bytes currently admitted, and sessions resident. */
 int qtask_server_usage(qtask_server_t s, uint64_t *bytes, int32_t *resident);
+/* Largest value the admitted bytes reached since the server was created
+ * (never above budget_bytes). */
+int qtask_server_peak_bytes(qtask_server_t s, uint64_t *peak);
 
 #ifdef __cplusplus
 }

@@ -60,7 +60,8 @@ int Session::autotune() {
         }
     }
     if (ops.empty()) return QTASK_OK;
-    const auto key = std::make_tuple(opts.device, n_int, dtype, opts.fusion, opts.fuse_width, mix_signature(ops));
+    const auto key = std::make_tuple(opts.device, n_int, dtype, opts.fusion, opts.fuse_width * 2 + opts.relabel,
+                                     mix_signature(ops));
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find(key);
@@ -72,8 +73,19 @@ int Session::autotune() {
             return QTASK_OK;
         }
     }
+    // the timing runs need a state buffer; a session that had none gets it
+    // back freed, so tuning leaves no memory behind that a serving budget
+    // did not charge
+    const bool had_state = state_.p != nullptr;
     rc = ensure_state();
     if (rc != QTASK_OK) return rc;
+    struct FreeState {
+        Session *s;
+        bool keep;
+        ~FreeState() {
+            if (!keep) s->release_state();
+        }
+    } free_state{this, had_state};
     // candidates: tile shape (b, c) at the session's fusion mode; under
     // QTASK_FUSE_AUTO also every stage fused into a dense k-qubit unitary on
     // the matrix cores, k = 4..6 (the fusion width is tuned with the shape)
@@ -81,8 +93,11 @@ int Session::autotune() {
         int b, c, fusion, k;
     };
     std::vector<Cand> cand;
+    // with relabelling every tile position can hold a needed qubit, so
+    // more contiguous low bits cost fewer extra passes: try up to 8
+    const std::vector<int> lows = opts.relabel ? std::vector<int>{3, 4, 5, 6, 7, 8} : std::vector<int>{3, 4, 5, 6, 8};
     for (int b : {10, 11, 12, 13})
-        for (int c : {3, 4, 5, 6, 8})
+        for (int c : lows)
             if (b <= n_int && c <= b - 3 && (opts.fusion != QTASK_FUSE_DENSE || b - opts.fuse_width >= 4))
                 cand.push_back({b, c, opts.fusion, opts.fuse_width});
     if (opts.fusion == QTASK_FUSE_AUTO)
@@ -107,6 +122,7 @@ int Session::autotune() {
         pp.fusion = bc.fusion;
         pp.fuse_k = bc.k;
         pp.swz = dtype == QTASK_C128 ? 4 : 5;
+        pp.relabel = opts.relabel;
         std::vector<SegmentPlan> sps(parts.size());
         try {
             for (size_t i = 0; i < parts.size(); ++i) sps[i] = plan_segment(parts[i], pp);

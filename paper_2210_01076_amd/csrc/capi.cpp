@@ -100,6 +100,7 @@ int qtask_opts_default(qtask_opts *o) {
     o->renorm = 1;
     o->autotune = 0;
     o->closed_mode = 1;
+    o->relabel = -1;
     return QTASK_OK;
 }
 
@@ -141,6 +142,8 @@ int qtask_create(int n_qubits, qtask_dtype dtype, const qtask_opts *user, qtask_
             std::min(o.tile_bits, std::max(n_qubits, QK_MIN_TILE_BITS)) < 10)
             return QTASK_E_UNSUPPORTED;  // matrix-core stages need tiles of >= 2^10 amplitudes
         if (o.ckpt_interval < 1 || o.max_ckpts < -1) return QTASK_E_ARG;
+        if (o.relabel < -1 || o.relabel > 1) return QTASK_E_ARG;
+        if (o.relabel == -1) o.relabel = std::max(n_qubits, QK_MIN_TILE_BITS) >= 26 ? 1 : 0;
         if (o.device < QTASK_DEVICE_NONE) return QTASK_E_ARG;
         if ((o.alloc == nullptr) != (o.free == nullptr)) return QTASK_E_ARG;
         if (o.device >= 0) {

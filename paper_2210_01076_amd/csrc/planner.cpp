@@ -309,32 +309,53 @@ struct Packer {
     int coalesce_bits() const { return pp.dtype == 0 ? 3 : 4; }
 
     void finish_pass(PPass &ps) const {
-        auto empty_stage = [&] {
-            PStage st;
-            for (int p = pp.b - QK_G; p < pp.b; ++p) st.tbits.push_back(p);
-            return st;
-        };
         const int lowb = std::min(coalesce_bits(), pp.b - QK_G);
-        auto touches_low = [&](const PStage &st) {
+        // tile bits on the lowest physical positions when the pass loads
+        // (0, 1, ...) and when it stores (in order of their store position)
+        std::vector<int> low_in, low_out;
+        for (int q = 0; q < lowb; ++q) {
+            for (int p = 0; p < pp.b; ++p)
+                if (ps.qlist[size_t(p)] == q) low_in.push_back(p);
+            for (int p = 0; p < pp.b; ++p)
+                if (ps.out_pos(p) == q) low_out.push_back(p);
+        }
+        auto touches = [](const PStage &st, const std::vector<int> &bits) {
             for (int p : st.tbits)
-                if (p < lowb) return true;
+                if (std::find(bits.begin(), bits.end(), p) != bits.end()) return true;
             return false;
         };
+        // a load- or store-only stage: registers on the highest tile bits
+        // that are not among `avoid`
+        auto empty_stage = [&](const std::vector<int> &avoid) {
+            PStage st;
+            for (int p = pp.b - 1; p >= 0 && int(st.tbits.size()) < QK_G; --p)
+                if (std::find(avoid.begin(), avoid.end(), p) == avoid.end()) st.tbits.push_back(p);
+            std::sort(st.tbits.begin(), st.tbits.end());
+            return st;
+        };
         // the first stage loads and the last one stores: both must be
-        // register stages whose registers avoid the lowest tile bits; when
-        // they are not, a plain load (store) stage goes through LDS instead
-        if (ps.stages.empty() || ps.stages.front().mfma || touches_low(ps.stages.front()))
-            ps.stages.insert(ps.stages.begin(), empty_stage());
-        if (ps.stages.back().mfma || (ps.stages.size() > 1 && touches_low(ps.stages.back())))
-            ps.stages.push_back(empty_stage());
+        // register stages whose registers avoid the tile bits that must vary
+        // across lanes for coalescing; when they are not, a plain load
+        // (store) stage goes through LDS instead.  A relabelling pass loads
+        // and stores through different global maps, so it needs two stages.
+        if (ps.stages.empty() || ps.stages.front().mfma || touches(ps.stages.front(), low_in))
+            ps.stages.insert(ps.stages.begin(), empty_stage(low_in));
+        if (ps.stages.back().mfma || (ps.stages.size() > 1 && touches(ps.stages.back(), low_out)) ||
+            (ps.stages.size() == 1 && ps.relabels()))
+            ps.stages.push_back(empty_stage(low_out));
         for (const auto &st : ps.stages) ps.has_mfma = ps.has_mfma || st.mfma;
-        // their lowest lane bits are the lowest tile bits, in order (what
+        // their lowest lane bits are those tile bits, in order (what
         // coalescing needs); the next ones are chosen for the banks
-        for (PStage *st : {&ps.stages.front(), &ps.stages.back()}) {
+        for (int which = 0; which < 2; ++which) {
+            PStage *st = which == 0 ? &ps.stages.front() : &ps.stages.back();
+            const std::vector<int> &lowv = which == 0 ? low_in : low_out;
             std::vector<int> others, low;
             for (int p = 0; p < pp.b; ++p)
                 if (std::find(st->tbits.begin(), st->tbits.end(), p) == st->tbits.end()) others.push_back(p);
-            for (int p = 0; p < lowb && p < int(others.size()) && others[p] == p; ++p) low.push_back(p);
+            for (int p : lowv) {
+                if (std::find(others.begin(), others.end(), p) == others.end()) break;
+                low.push_back(p);
+            }
             st->tpos = lane_order(others, pp.swz, low);
         }
     }
@@ -427,7 +448,25 @@ struct Packer {
         }
     }
 
+    // One pass: its physical tile positions, the ops it runs (already on
+    // physical positions) and where it stores each tile bit.
+    PPass make_pass(uint64_t pmask, const std::vector<const LGate *> &pops, const std::vector<int> *out_of) const {
+        PPass ps;
+        ps.qmask = pmask;
+        for (int q = 0; q < pp.n; ++q)
+            if ((pmask >> q) & 1) ps.qlist.push_back(q);
+        if (out_of) {
+            for (int q : ps.qlist) ps.out.push_back((*out_of)[size_t(q)]);
+            if (ps.out == ps.qlist) ps.out.clear();
+        }
+        ps.n_gates = int(pops.size());
+        pack_stages(ps, pops);
+        finish_pass(ps);
+        return ps;
+    }
+
     std::vector<PPass> pack_passes(const std::vector<LGate> &ops) const {
+        if (pp.relabel) return pack_passes_relabel(ops);
         // keep room for a three-qubit gate on qubits above the low bits, so
         // every pass can take at least the first pending gate
         const int c = std::max(0, std::min(pp.c, pp.b - 3));
@@ -451,20 +490,158 @@ struct Packer {
             const uint64_t Q = choose_set(mask, rem, low, pp.b, 0, fill);
             split_ops(mask, rem, Q, 0, take, left);
             if (take.empty()) throw std::logic_error("planner made no progress");
-            PPass ps;
-            ps.qmask = Q;
-            for (int q = 0; q < pp.n; ++q)
-                if ((Q >> q) & 1) ps.qlist.push_back(q);
             std::vector<const LGate *> pops;
             pops.reserve(take.size());
             for (size_t idx : take) pops.push_back(&ops[idx]);
-            ps.n_gates = int(pops.size());
-            pack_stages(ps, pops);
-            finish_pass(ps);
-            passes.push_back(std::move(ps));
+            passes.push_back(make_pass(Q, pops, nullptr));
             rem.swap(left);
         }
         return passes;
+    }
+
+    // Passes with relabelling.  The sets are chosen over circuit qubits as
+    // above, starting from the qubits that sit in the c low positions; the
+    // ops are then moved to the physical positions of their qubits.  At the
+    // end of a pass the c tile qubits whose next use comes first move into
+    // the low positions (those already there keep their slot), and every
+    // other tile qubit goes back to its own position when that position is
+    // in the tile.  The segment's last pass puts back every qubit whose own
+    // position it holds; passes without ops then put back the rest.
+    std::vector<PPass> pack_passes_relabel(const std::vector<LGate> &ops) const {
+        const int n = pp.n, b = pp.b;
+        const int c = std::max(0, std::min(pp.c, pp.b - 3));
+        std::vector<int> pos(static_cast<size_t>(n)), occ(static_cast<size_t>(n));  // circuit qubit -> position, position -> qubit
+        for (int q = 0; q < n; ++q) pos[size_t(q)] = occ[size_t(q)] = q;
+        std::vector<uint64_t> mask(ops.size());
+        for (size_t i = 0; i < ops.size(); ++i) mask[i] = ops[i].mask();
+        std::vector<size_t> rem(ops.size());
+        for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
+        std::vector<PPass> passes;
+        std::vector<size_t> take, left;
+        std::vector<LGate> phys;  // the current pass's ops on physical positions
+        constexpr size_t kNever = SIZE_MAX;
+        auto fill = [&](uint64_t Q) {
+            for (int q = 0; q < n && popc(Q) < b; ++q) Q |= uint64_t(1) << q;
+            return Q;
+        };
+        // assign the tile's qubits to the tile's positions: `hot` (in order)
+        // to the low positions, qubits already in a low position keep it;
+        // then every other qubit to its own position when that is free,
+        // the rest to the remaining positions in ascending order.  With no
+        // hot qubits every qubit whose own position is in the tile goes there.
+        auto assign = [&](const std::vector<int> &tq, const std::vector<int> &hot, std::vector<int> &newpos) {
+            std::vector<int> freep;
+            for (int q : tq) freep.push_back(pos[size_t(q)]);
+            std::sort(freep.begin(), freep.end());
+            auto take_pos = [&](int p) { freep.erase(std::find(freep.begin(), freep.end(), p)); };
+            std::vector<char> done(static_cast<size_t>(n), 0);
+            if (hot.empty())
+                for (int q : tq)
+                    if (std::find(freep.begin(), freep.end(), q) != freep.end()) {
+                        newpos[size_t(q)] = q;
+                        take_pos(q);
+                        done[size_t(q)] = 1;
+                    }
+            for (int q : hot)
+                if (pos[size_t(q)] < c) { newpos[size_t(q)] = pos[size_t(q)]; take_pos(pos[size_t(q)]); done[size_t(q)] = 1; }
+            for (int q : hot)
+                if (!done[size_t(q)]) {
+                    const int p = freep.front();  // a low position (the low ones are all in the tile)
+                    newpos[size_t(q)] = p;
+                    take_pos(p);
+                    done[size_t(q)] = 1;
+                }
+            for (int q : tq)
+                if (!done[size_t(q)] && std::find(freep.begin(), freep.end(), q) != freep.end()) {
+                    newpos[size_t(q)] = q;
+                    take_pos(q);
+                    done[size_t(q)] = 1;
+                }
+            for (int q : tq)
+                if (!done[size_t(q)]) {
+                    newpos[size_t(q)] = freep.front();
+                    take_pos(freep.front());
+                }
+        };
+        auto apply = [&](const std::vector<int> &tq, const std::vector<int> &newpos, std::vector<int> &out_of) {
+            // out_of: physical position before -> after, for the tile's positions
+            for (int q : tq) out_of[size_t(pos[size_t(q)])] = newpos[size_t(q)];
+            for (int q : tq) {
+                pos[size_t(q)] = newpos[size_t(q)];
+                occ[size_t(newpos[size_t(q)])] = q;
+            }
+        };
+        std::vector<int> newpos(static_cast<size_t>(n)), out_of(static_cast<size_t>(n));
+        while (!rem.empty()) {
+            uint64_t start = 0;
+            for (int p = 0; p < c; ++p) start |= uint64_t(1) << occ[size_t(p)];
+            const uint64_t Q = choose_set(mask, rem, start, b, 0, fill);
+            split_ops(mask, rem, Q, 0, take, left);
+            if (take.empty()) throw std::logic_error("planner made no progress");
+            std::vector<int> tq;
+            uint64_t pmask = 0;
+            for (int q = 0; q < n; ++q)
+                if ((Q >> q) & 1) {
+                    tq.push_back(q);
+                    pmask |= uint64_t(1) << pos[size_t(q)];
+                }
+            phys.clear();
+            phys.reserve(take.size());
+            for (size_t idx : take) {
+                LGate g = ops[idx];
+                for (int j = 0; j < g.nq; ++j) g.q[j] = pos[size_t(g.q[j])];
+                phys.push_back(std::move(g));
+            }
+            std::vector<const LGate *> pops;
+            for (const LGate &g : phys) pops.push_back(&g);
+            rem.swap(left);
+            // where the tile's qubits go
+            std::vector<int> hot;
+            if (!rem.empty()) {
+                std::vector<size_t> next(static_cast<size_t>(n), kNever);
+                size_t found = 0;
+                for (size_t k = 0; k < rem.size() && found < tq.size(); ++k) {
+                    const LGate &g = ops[rem[k]];
+                    for (int j = 0; j < g.nq; ++j)
+                        if (next[size_t(g.q[j])] == kNever && ((Q >> g.q[j]) & 1)) {
+                            next[size_t(g.q[j])] = k;
+                            ++found;
+                        }
+                }
+                hot = tq;
+                std::stable_sort(hot.begin(), hot.end(), [&](int x, int y) {
+                    if (next[size_t(x)] != next[size_t(y)]) return next[size_t(x)] < next[size_t(y)];
+                    return (pos[size_t(x)] < c) > (pos[size_t(y)] < c);
+                });
+                hot.resize(size_t(c));
+            }
+            assign(tq, hot, newpos);
+            apply(tq, newpos, out_of);
+            passes.push_back(make_pass(pmask, pops, &out_of));
+        }
+        // passes without ops put back the qubits still away from their own
+        // position: each takes the low positions plus, qubit by qubit, the
+        // current and the own position of displaced qubits while they fit
+        for (int guard = 0; guard < 4 * n; ++guard) {
+            std::vector<int> away;
+            for (int q = 0; q < n; ++q)
+                if (pos[size_t(q)] != q) away.push_back(q);
+            if (away.empty()) return passes;
+            uint64_t pmask = (uint64_t(1) << c) - 1;
+            for (int q : away) {
+                const uint64_t add = (uint64_t(1) << pos[size_t(q)]) | (uint64_t(1) << q);
+                if (popc(pmask | add) <= b) pmask |= add;
+            }
+            for (int p = 0; p < n && popc(pmask) < b; ++p) pmask |= uint64_t(1) << p;
+            std::vector<int> tq;
+            for (int p = 0; p < n; ++p)
+                if ((pmask >> p) & 1) tq.push_back(occ[size_t(p)]);
+            std::sort(tq.begin(), tq.end());
+            assign(tq, {}, newpos);
+            apply(tq, newpos, out_of);
+            passes.push_back(make_pass(pmask, {}, &out_of));
+        }
+        throw std::logic_error("relabelling did not return to the plain layout");
     }
 };
 
@@ -516,13 +693,18 @@ void pack_blob(SegmentPlan &sp) {
         P.n_thr = uint32_t(n_thr);
         P.stage_begin = uint32_t(si);
         P.stage_count = uint32_t(ps.stages.size());
-        for (const PStage &st : ps.stages) {
+        // the first stage loads tile bit p from position qlist[p], the last
+        // one stores it to out_pos(p) (the same unless the pass relabels)
+        auto goff_out = [&](int p) { return uint64_t(1) << ps.out_pos(p); };
+        for (size_t sti = 0; sti < ps.stages.size(); ++sti) {
+            const PStage &st = ps.stages[sti];
             KStage &S = ks[si++];
             std::memset(&S, 0, sizeof(S));
             const int W = int(st.tbits.size());
+            const bool store = sti + 1 == ps.stages.size();
             if (!st.mfma) {
-                for (int j = 0; j < G; ++j) S.g_bit[j] = goff(st.tbits[j]);
-                for (int j = 0; j < n_thr; ++j) S.g_thr[j] = goff(st.tpos[j]);
+                for (int j = 0; j < G; ++j) S.g_bit[j] = store ? goff_out(st.tbits[j]) : goff(st.tbits[j]);
+                for (int j = 0; j < n_thr; ++j) S.g_thr[j] = store ? goff_out(st.tpos[j]) : goff(st.tpos[j]);
             }
             if (st.mfma) {
                 S.kind = KSTAGE_MFMA;
@@ -593,7 +775,7 @@ uint64_t segment_hash(const std::vector<LGate> &ops, const PlanParams &pp) {
     // kinds, qubits and matrices
     auto mix = hash_mix;
     uint64_t h = 0x243f6a8885a308d3ull;
-    const int64_t params[7] = {pp.n, pp.b, pp.c, pp.dtype, pp.fusion, pp.fuse_k, pp.swz};
+    const int64_t params[8] = {pp.n, pp.b, pp.c, pp.dtype, pp.fusion, pp.fuse_k, pp.swz, pp.relabel};
     for (int64_t v : params) h = mix(h, uint64_t(v));
     for (const auto &g : ops) {
         h = mix(h, uint64_t(g.kop) | (uint64_t(uint8_t(g.nq)) << 8) | (uint64_t(uint16_t(g.q[0])) << 16) |
@@ -727,6 +909,41 @@ std::string validate_plan(const SegmentPlan &sp) {
     return "";
 }
 
+// The blob records of pass pi as the kernel reads them: deposit runs, and
+// per stage the LDS maps, the global maps, the op records and (matrix-core
+// stages) the row and column slots.
+static void blob_json(std::ostringstream &o, const SegmentPlan &sp, size_t pi) {
+    const KPass &P = reinterpret_cast<const KPass *>(sp.blob.data())[pi];
+    const KStage *ks = reinterpret_cast<const KStage *>(sp.blob.data() + sp.off_stage);
+    const KOp *ko = reinterpret_cast<const KOp *>(sp.blob.data() + sp.off_op);
+    auto arr = [&](const char *name, auto *v, size_t len) {
+        o << ",\"" << name << "\":[";
+        for (size_t i = 0; i < len; ++i) o << (i ? "," : "") << uint64_t(v[i]);
+        o << "]";
+    };
+    o << "{\"n_thr\":" << P.n_thr;
+    arr("runs", P.run, P.n_runs);
+    o << ",\"stages\":[";
+    for (uint32_t s = 0; s < P.stage_count; ++s) {
+        const KStage &S = ks[P.stage_begin + s];
+        o << (s ? "," : "") << "{\"kind\":" << S.kind << ",\"k\":" << S.k << ",\"coef\":" << S.coef;
+        arr("reg_bit", S.reg_bit, QK_G);
+        arr("thr_off", S.thr_off, QK_MAX_THR_BITS);
+        arr("g_bit", S.g_bit, QK_G);
+        arr("g_thr", S.g_thr, QK_MAX_THR_BITS);
+        arr("row_off", S.row_off, size_t(1) << std::min<uint32_t>(S.k, QK_MAX_DENSE_K));
+        arr("col_off", S.col_off, S.n_col_bits);
+        o << ",\"ops\":[";
+        for (uint32_t k = 0; k < S.op_count; ++k) {
+            const KOp &op = ko[S.op_begin + k];
+            o << (k ? "," : "") << "[" << int(op.type) << "," << int(op.a) << "," << int(op.b) << "," << int(op.c)
+              << "," << op.coef << "]";
+        }
+        o << "]}";
+    }
+    o << "]}";
+}
+
 std::string plan_json(const SegmentPlan &sp, bool with_matrices) {
     std::ostringstream o;
     o.precision(17);
@@ -738,6 +955,8 @@ std::string plan_json(const SegmentPlan &sp, bool with_matrices) {
         if (pi) o << ",";
         o << "{\"qubits\":[";
         for (size_t i = 0; i < ps.qlist.size(); ++i) o << (i ? "," : "") << ps.qlist[i];
+        o << "],\"out\":[";
+        for (int p = 0; p < int(ps.qlist.size()); ++p) o << (p ? "," : "") << ps.out_pos(p);
         o << "],\"gates\":" << ps.n_gates << ",\"stages\":[";
         for (size_t si = 0; si < ps.stages.size(); ++si) {
             const PStage &st = ps.stages[si];
@@ -773,9 +992,26 @@ std::string plan_json(const SegmentPlan &sp, bool with_matrices) {
             }
             o << "}";
         }
-        o << "]}";
+        o << "]";
+        if (with_matrices) {
+            o << ",\"kernel\":";
+            blob_json(o, sp, pi);
+        }
+        o << "}";
     }
-    o << "]}";
+    o << "]";
+    if (with_matrices) {
+        // the coefficient array (as the kernel reads it, in the session dtype)
+        const size_t ncoef = (sp.blob.size() - sp.off_coef) / (sp.pp.dtype == 0 ? sizeof(double) : sizeof(float));
+        o << ",\"coefs\":[";
+        for (size_t i = 0; i < ncoef; ++i) {
+            const double v = sp.pp.dtype == 0 ? reinterpret_cast<const double *>(sp.blob.data() + sp.off_coef)[i]
+                                              : double(reinterpret_cast<const float *>(sp.blob.data() + sp.off_coef)[i]);
+            o << (i ? "," : "") << v;
+        }
+        o << "]";
+    }
+    o << "}";
     return o.str();
 }
 

@@ -20,6 +20,7 @@ struct PlanParams {
     int fusion = 0;     // qtask_fusion
     int fuse_k = 4;     // width of dense fused unitaries
     int swz = 4;        // LDS swizzle width in bits
+    int relabel = 0;    // 1: passes may relabel qubits (see PPass::out)
 };
 
 struct PStage {
@@ -31,12 +32,22 @@ struct PStage {
     double flops = 0;         // algorithmic flops per amplitude
 };
 
+// Qubit relabelling.  Ops and tile bits name physical bit positions of the
+// state buffer.  Without relabelling a circuit qubit always sits at its own
+// position; with it, a pass may store tile bit p at position out[p] instead
+// of qlist[p] (a permutation of the tile's positions), so that the qubits
+// the next passes need come to sit in the contiguous low positions every
+// tile holds.  Each segment starts and ends with every qubit at its own
+// position, so checkpoints and the final state keep the plain layout.
 struct PPass {
-    std::vector<int> qlist;   // global qubit of tile bit p
+    std::vector<int> qlist;   // physical position of tile bit p (where it is loaded from)
+    std::vector<int> out;     // physical position tile bit p is stored to (empty: qlist)
     std::vector<PStage> stages;
     uint64_t qmask = 0;
     int n_gates = 0;          // source gates applied in this pass
     bool has_mfma = false;    // some stage runs on the matrix cores
+    bool relabels() const { return !out.empty() && out != qlist; }
+    int out_pos(int p) const { return out.empty() ? qlist[size_t(p)] : out[size_t(p)]; }
 };
 
 struct SegmentPlan {

@@ -1,10 +1,14 @@
 // Serving: many sessions resident on one device, updated by a stream of
 // modify+update requests with continuous batching.
 //
-//  - Admission: a session holds device memory (state + checkpoints) only
-//    while resident; it is admitted when its bytes fit the budget, evicting
-//    idle sessions (least recently used first) when needed.  Requests of a
-//    session that cannot be admitted wait in its queue.
+//  - Admission: a session holds device memory (state, checkpoints, plans and
+//    scratch) only while resident.  A request's edits are applied and its
+//    update planned on the host first; the session is then charged the
+//    bytes it will hold after that update (which may have grown: added
+//    levels add checkpoints) and admitted when they fit the budget, evicting
+//    idle sessions (least recently used first) when needed.  A request that
+//    cannot be admitted yet waits; one that can never fit fails with
+//    QTASK_E_NOMEM and its edits are undone.
 //  - Large sessions (n >= small_qubits) replay on their own streams (default
 //    priority), up to max_inflight at once, so their passes overlap on the
 //    device.
@@ -66,7 +70,8 @@ struct SSession {
     bool small = false;
     bool batched = false;   // current request runs in the batched ticks
     bool counted = false;   // current request holds a large-session slot
-    uint64_t bytes = 0;
+    bool waiting = false;   // current request is planned and waits for memory
+    uint64_t bytes = 0;     // bytes charged to the budget while resident
     double last_used = 0;
     std::deque<Request> q;
     Request cur;
@@ -103,7 +108,10 @@ struct qtask_server_s {
     std::unordered_map<uint64_t, int32_t> pending_ticket;  // ticket -> session
     uint64_t next_ticket = 1;
     uint64_t used = 0;
+    uint64_t peak_used = 0;
     int32_t resident = 0;
+    std::vector<int32_t> waiting;        // planned requests waiting for memory, in start order
+    std::vector<int32_t> replan;         // waiting requests whose session was evicted meanwhile
     bool stop = false;
     double t0 = 0;
     std::thread worker;
@@ -120,7 +128,9 @@ struct qtask_server_s {
     int start_small_tick(std::vector<int32_t> &ready, std::vector<int32_t> &group);
     int launch_rounds(int dtype, uint32_t threads, uint32_t lds, uint32_t rounds, uint32_t groups);
     void finish(int32_t sid, double done_ms);
-    int admit(int32_t sid);
+    int admit(int32_t sid, uint64_t need);
+    void evict(int32_t victim);
+    int32_t lru_victim(int32_t except) const;
 };
 
 namespace {
@@ -165,32 +175,51 @@ int apply_edit(Session *s, const qtask_edit &e) {
 
 }  // namespace
 
-// 1: resident (admitted now or before), 0: must wait for memory, -1: can
-// never fit the budget.  Called with the lock held.
-int qtask_server_s::admit(int32_t sid) {
-    SSession &ss = sess[sid];
-    if (ss.resident) return 1;
-    const uint64_t need = ss.s->planned_bytes();
-    if (need > opts.budget_bytes) return -1;
-    while (used + need > opts.budget_bytes) {
-        // evict the least recently used idle resident session
-        int32_t victim = -1;
-        for (size_t i = 0; i < sess.size(); ++i) {
-            const SSession &o = sess[i];
-            if (!o.resident || o.busy || !o.q.empty()) continue;
-            if (victim < 0 || o.last_used < sess[victim].last_used) victim = int32_t(i);
-        }
-        if (victim < 0) return 0;
-        sess[victim].s->release_device();
-        used -= sess[victim].bytes;
-        sess[victim].bytes = 0;
-        sess[victim].resident = false;
-        --resident;
+// Least recently used resident session that is idle (nothing running,
+// nothing planned, nothing queued), or -1.  Called with the lock held.
+int32_t qtask_server_s::lru_victim(int32_t except) const {
+    int32_t victim = -1;
+    for (size_t i = 0; i < sess.size(); ++i) {
+        const SSession &o = sess[i];
+        if (int32_t(i) == except || !o.resident || o.busy || !o.q.empty()) continue;
+        if (victim < 0 || o.last_used < sess[victim].last_used) victim = int32_t(i);
     }
-    ss.resident = true;
+    return victim;
+}
+
+// Free a resident session's device memory (its next update re-simulates
+// from the start).  Called with the lock held; the session is not busy, or
+// busy but neither running nor committed.
+void qtask_server_s::evict(int32_t victim) {
+    SSession &v = sess[victim];
+    v.s->release_device();
+    used -= v.bytes;
+    v.bytes = 0;
+    v.resident = false;
+    --resident;
+}
+
+// Charge `need` bytes (the session's footprint after its planned update):
+// 1 admitted (resident, charged at least `need`), 0 must wait for memory,
+// -1 can never fit the budget.  Called with the lock held.
+int qtask_server_s::admit(int32_t sid, uint64_t need) {
+    SSession &ss = sess[sid];
+    if (need > opts.budget_bytes) return -1;
+    const uint64_t have = ss.resident ? ss.bytes : 0;
+    if (need <= have) return 1;
+    const uint64_t extra = need - have;
+    while (used + extra > opts.budget_bytes) {
+        const int32_t victim = lru_victim(sid);
+        if (victim < 0) return 0;
+        evict(victim);
+    }
+    if (!ss.resident) {
+        ss.resident = true;
+        ++resident;
+    }
     ss.bytes = need;
-    used += need;
-    ++resident;
+    used += extra;
+    peak_used = std::max(peak_used, used);
     return 1;
 }
 
@@ -215,9 +244,21 @@ void qtask_server_s::finish(int32_t sid, double done_ms) {
     r.stats.wall_ms = done_ms - ss.start_ms;
     const uint64_t nb = s->device_bytes();
     std::lock_guard<std::mutex> lk(mu);
-    // the session may have grown (levels added): recharge its bytes
-    if (nb > ss.bytes) { used += nb - ss.bytes; ss.bytes = nb; }
+    // charge what the session holds now: no more than admitted (the
+    // admission charged its footprint after this update), less when the
+    // update shrank it
+    if (ss.resident) {
+        used = used - ss.bytes + nb;
+        ss.bytes = nb;
+        peak_used = std::max(peak_used, used);
+        while (used > opts.budget_bytes) {
+            const int32_t victim = lru_victim(sid);
+            if (victim < 0) break;
+            evict(victim);
+        }
+    }
     ss.busy = false;
+    ss.waiting = false;
     ss.last_used = done_ms;
     results[r.ticket] = r;
     pending_ticket.erase(r.ticket);
@@ -370,10 +411,10 @@ void qtask_server_s::run() {
     while (true) {
         // 1. take new work: oldest request first, as far as memory and launch
         //    slots allow
-        std::vector<std::pair<int32_t, int>> starts;  // session, admission result
+        std::vector<int32_t> starts;
         {
             std::unique_lock<std::mutex> lk(mu);
-            const bool any_busy = tick_inflight || inflight_large > 0;
+            const bool any_busy = tick_inflight || inflight_large > 0 || !waiting.empty() || !replan.empty();
             if (!any_busy && small_ready.empty()) {
                 cv_work.wait(lk, [&] {
                     if (stop) return true;
@@ -407,37 +448,103 @@ void qtask_server_s::run() {
             for (int32_t sid : order) {
                 SSession &ss = sess[sid];
                 if (!ss.small && inflight_large >= opts.max_inflight) continue;
-                const int adm = admit(sid);
-                if (adm == 0) continue;  // waits for memory
                 ss.busy = true;
+                ss.batched = false;
+                ss.waiting = true;
                 ss.cur = std::move(ss.q.front());
                 ss.q.pop_front();
-                ss.counted = !ss.small && adm > 0;
+                ss.counted = !ss.small;
                 if (ss.counted) ++inflight_large;
-                starts.emplace_back(sid, adm);
+                starts.push_back(sid);
             }
         }
-        // 2. apply edits, plan, launch (outside the lock: only the worker
-        //    touches a busy session)
-        for (const auto &st : starts) {
-            const int32_t sid = st.first;
+        auto fail = [&](int32_t sid, int code, bool rollback) {
+            SSession &ss = sess[sid];
+            if (rollback) ss.s->rollback_edit_point();
+            ss.status = code;
+            if (ss.counted) --inflight_large;
+            ss.counted = false;
+            finish(sid, clock());
+        };
+        // waiting sessions whose memory was freed while they waited lost
+        // their plans: plan them again (now a full simulation)
+        for (int32_t sid : replan) {
+            SSession &ss = sess[sid];
+            const int rc = ss.s->plan_update(false);
+            if (rc != QTASK_OK) {
+                fail(sid, rc, true);
+                continue;
+            }
+            waiting.push_back(sid);
+        }
+        replan.clear();
+        // 2. apply the edits and plan the update on the host (outside the
+        //    lock: only the worker touches a busy session).  A request is
+        //    all or nothing: a failed edit or plan undoes its edits.
+        for (int32_t sid : starts) {
             SSession &ss = sess[sid];
             ss.start_ms = clock();
-            ss.status = st.second < 0 ? QTASK_E_NOMEM : QTASK_OK;
-            for (size_t i = 0; i < ss.cur.edits.size() && ss.status == QTASK_OK; ++i)
-                ss.status = apply_edit(ss.s, ss.cur.edits[i]);
-            if (ss.status == QTASK_OK) {
-                // a failed edit leaves the state stale but intact; a failed
-                // plan or device step leaves it unknown
-                ss.status = ss.s->init_device();
-                if (ss.status == QTASK_OK) ss.status = ss.s->ensure_tuned();
-                if (ss.status == QTASK_OK) ss.status = ss.s->prepare(false);
-                if (ss.status != QTASK_OK) ss.s->invalidate();
+            ss.status = QTASK_OK;
+            ss.s->save_edit_point();
+            int rc = QTASK_OK;
+            for (size_t i = 0; i < ss.cur.edits.size() && rc == QTASK_OK; ++i) rc = apply_edit(ss.s, ss.cur.edits[i]);
+            if (rc == QTASK_OK) rc = ss.s->init_device();
+            if (rc == QTASK_OK) rc = ss.s->ensure_tuned();
+            if (rc == QTASK_OK) rc = ss.s->plan_update(false);
+            if (rc != QTASK_OK) {
+                if (rc == QTASK_E_DEVICE) ss.s->invalidate();
+                fail(sid, rc, true);
+                continue;
             }
-            if (ss.status != QTASK_OK) {
-                if (ss.counted) --inflight_large;
-                ss.counted = false;
-                finish(sid, clock());
+            ss.waiting = true;
+            waiting.push_back(sid);
+        }
+        // 3. admission of the planned requests, oldest start first, by the
+        //    bytes each session holds after its update
+        std::vector<int32_t> commits, never;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            std::vector<int32_t> still;
+            for (int32_t sid : waiting) {
+                const int adm = admit(sid, sess[sid].s->bytes_after_commit());
+                if (adm > 0) commits.push_back(sid);
+                else if (adm < 0) never.push_back(sid);
+                else still.push_back(sid);
+            }
+            // Nothing running can free memory and nothing was admitted: the
+            // waiting sessions block one another.  Free the others' memory
+            // (they re-simulate later) so that the oldest one fits.
+            if (commits.empty() && !still.empty() && !tick_inflight && small_ready.empty()) {
+                bool running = false;
+                for (const auto &o : sess) running = running || (o.busy && !o.waiting);
+                if (!running) {
+                    std::vector<int32_t> keep{still[0]};
+                    for (size_t i = 1; i < still.size(); ++i) {
+                        if (sess[still[i]].resident) {
+                            evict(still[i]);
+                            replan.push_back(still[i]);
+                        } else {
+                            keep.push_back(still[i]);
+                        }
+                    }
+                    still.swap(keep);
+                    if (admit(still[0], sess[still[0]].s->bytes_after_commit()) > 0) {
+                        commits.push_back(still[0]);
+                        still.erase(still.begin());
+                    }
+                }
+            }
+            waiting.swap(still);
+        }
+        for (int32_t sid : never) fail(sid, QTASK_E_NOMEM, true);
+        // 4. commit (allocate, upload) and launch
+        for (int32_t sid : commits) {
+            SSession &ss = sess[sid];
+            ss.waiting = false;
+            int rc = ss.s->commit_device();
+            if (rc != QTASK_OK) {
+                if (rc == QTASK_E_DEVICE) ss.s->invalidate();
+                fail(sid, rc, rc != QTASK_E_DEVICE);
                 continue;
             }
             // the batched kernel has no matrix-core stages: such plans run
@@ -448,18 +555,16 @@ void qtask_server_s::run() {
             if (ss.batched) {
                 // plan uploads went to the session's stream
                 if (hipStreamSynchronize(ss.s->stream) != hipSuccess) {
-                    ss.status = QTASK_E_DEVICE;
-                    finish(sid, clock());
+                    ss.s->invalidate();
+                    fail(sid, QTASK_E_DEVICE, false);
                     continue;
                 }
                 small_ready.push_back(sid);
             } else if (ss.s->enqueue_prepared(ss.s->stream) != QTASK_OK ||
                        hipEventRecord(ss.done, ss.s->stream) != hipSuccess) {
-                ss.status = QTASK_E_DEVICE;
                 (void)hipStreamSynchronize(ss.s->stream);
-                if (ss.counted) --inflight_large;
-                ss.counted = false;
-                finish(sid, clock());
+                ss.s->invalidate();
+                fail(sid, QTASK_E_DEVICE, false);
             }
         }
         // 3. a batched tick when none is running; sessions that become ready
@@ -480,7 +585,9 @@ void qtask_server_s::run() {
         bool progressed = false;
         for (size_t i = 0; i < sess.size(); ++i) {
             SSession &ss = sess[i];
-            if (!ss.busy || ss.batched) continue;
+            // only launched requests on the session's own stream: batched
+            // ones finish with their tick, planned ones still wait for memory
+            if (!ss.busy || ss.batched || ss.waiting) continue;
             const hipError_t q = hipEventQuery(ss.done);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) ss.status = QTASK_E_DEVICE;
@@ -692,6 +799,13 @@ int qtask_server_usage(qtask_server_t sv, uint64_t *bytes, int32_t *resident) {
     std::lock_guard<std::mutex> lk(sv->mu);
     *bytes = sv->used;
     *resident = sv->resident;
+    return QTASK_OK;
+}
+
+int qtask_server_peak_bytes(qtask_server_t sv, uint64_t *peak) {
+    if (!sv || !peak) return QTASK_E_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *peak = sv->peak_used;
     return QTASK_OK;
 }
 

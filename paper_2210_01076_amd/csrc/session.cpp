@@ -14,6 +14,7 @@
 #include "session.h"
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <future>
@@ -113,6 +114,8 @@ uint64_t Session::device_bytes() const {
     uint64_t b = state_.bytes;
     for (const auto &kv : ckpts_) b += kv.second.buf.bytes;
     for (const auto &kv : plan_cache_) b += kv.second.dev_bytes;
+    b += (scalars_cap_ + partials_cap_) * sizeof(double) + u64_cap_ * sizeof(unsigned long long) +
+         tiles_cap_ * sizeof(uint32_t) + mask_cap_ * sizeof(uint64_t);
     return b;
 }
 
@@ -180,7 +183,7 @@ void Session::build_segments(const PlanParams &pp) {
         uint64_t k = 1469598103934665603ull;
         auto mix = [&](uint64_t v) { k = hash_mix(k, v); };
         mix(uint64_t(pp.b) | uint64_t(pp.c) << 8 | uint64_t(pp.fusion) << 16 | uint64_t(pp.fuse_k) << 24 |
-            uint64_t(pp.dtype) << 32);
+            uint64_t(pp.dtype) << 32 | uint64_t(pp.relabel) << 40);
         for (size_t i = sg.lo; i < sg.hi; ++i) {
             const Level &lv = circ.level_by_index(i);
             mix(lv.id);
@@ -197,24 +200,6 @@ size_t Session::slot_of(uint64_t anchor) {
     const size_t sl = next_slot_++;
     slots_.emplace(anchor, sl);
     return sl;
-}
-
-int Session::ensure_scalars(size_t slots) {
-    if (plan_only || scalars_cap_ / 2 >= slots) return QTASK_OK;
-    const size_t half = std::max<size_t>(2 * slots, 64);
-    double *p = static_cast<double *>(dalloc(2 * half * sizeof(double)));
-    if (!p) return QTASK_E_NOMEM;
-    if (d_scalars_) {
-        // keep the norms and scales of still-valid checkpoints
-        const size_t old = scalars_cap_ / 2;
-        HIPCHK(hipMemcpyAsync(p, d_scalars_, old * sizeof(double), hipMemcpyDeviceToDevice, stream));
-        HIPCHK(hipMemcpyAsync(p + half, d_scalars_ + old, old * sizeof(double), hipMemcpyDeviceToDevice, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-        dfree(d_scalars_);
-    }
-    d_scalars_ = p;
-    scalars_cap_ = 2 * half;
-    return QTASK_OK;
 }
 
 int Session::ensure_state() {
@@ -245,6 +230,8 @@ bool same_gate(const LGate &a, const LGate &b) {
 
 bool same_pass(const PPass &a, const PPass &b) {
     if (a.qlist != b.qlist || a.stages.size() != b.stages.size()) return false;
+    for (size_t p = 0; p < a.qlist.size(); ++p)
+        if (a.out_pos(int(p)) != b.out_pos(int(p))) return false;
     for (size_t i = 0; i < a.stages.size(); ++i) {
         const PStage &x = a.stages[i], &y = b.stages[i];
         if (x.tbits != y.tbits || x.mfma != y.mfma || x.ops.size() != y.ops.size()) return false;
@@ -257,8 +244,30 @@ bool same_pass(const PPass &a, const PPass &b) {
     return true;
 }
 
+// The store permutation of a relabelling pass as a sequence of exact
+// exchanges of two positions (SWAP ops, in order): the amplitude at a
+// position moves where the pass stores it.
+std::vector<LGate> relabel_swaps(const PPass &p) {
+    std::vector<LGate> out;
+    if (!p.relabels()) return out;
+    // cur[k] = position that now holds what was loaded from qlist[k]
+    std::vector<int> cur(p.qlist);
+    for (size_t k = 0; k < cur.size(); ++k) {
+        const int want = p.out_pos(int(k));
+        if (cur[k] == want) continue;
+        // whichever tile bit sits at `want` trades places with bit k
+        size_t j = 0;
+        while (cur[j] != want) ++j;
+        const int qa = cur[k], qb = want;
+        out.push_back(lower_gate(QTASK_SWAP, std::array<int, 2>{qa, qb}.data(), nullptr, 0));
+        std::swap(cur[k], cur[j]);
+    }
+    return out;
+}
+
 // f(BlockAction) for every op of the pass in program order; a fused dense
-// stage is one op on all of its qubits
+// stage is one op on all of its qubits; a relabelling pass ends with its
+// store permutation
 template <typename F>
 void for_pass_actions(const PPass &p, int beta, F &&f) {
     for (const auto &st : p.stages) {
@@ -270,6 +279,7 @@ void for_pass_actions(const PPass &p, int beta, F &&f) {
         }
         for (const auto &g : st.ops) f(block_action(g, beta));
     }
+    for (const auto &g : relabel_swaps(p)) f(block_action(g, beta));
 }
 
 uint64_t pext_tile(uint64_t x, const uint8_t *pos, uint32_t npos) {
@@ -285,6 +295,9 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     const int beta = std::min(opts.block_bits, n_int);
     const uint64_t nblocks = uint64_t(1) << (n_int - beta);
     if (nblocks > (uint64_t(1) << 22)) return QTASK_E_UNSUPPORTED;
+    // a state of one or two blocks gains nothing from a restricted replay,
+    // which costs a tile-list upload and a wait
+    if (nblocks < 4) return QTASK_E_UNSUPPORTED;
     const size_t nseg = segs_.size();
     if (s_edit >= nseg) return QTASK_E_UNSUPPORTED;
     // the segments after the edited one must be the same as at the last
@@ -338,13 +351,23 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
         std::sort(b.begin(), b.end(), by_key);
         BlockSet lb(nblocks);
         size_t i = 0, j = 0;
-        auto add = [&](const LGate &g) { for_rewritten_blocks(g, beta, nblocks, [&](uint64_t k) { lb.set(k); }); };
-        while (i < a.size() || j < b.size()) {
+        // an op of no controlled or phase form rewrites every block: the
+        // bound is saturated at once (relabelling moves many ops to other
+        // positions, and each would otherwise walk all blocks)
+        bool sat = false;
+        auto add = [&](const LGate &g) {
+            if (!(g.kop == KOP_P1 || g.kop == KOP_P2 || g.kop == KOP_CX || g.kop == KOP_CCX || g.kop == KOP_SWAP)) {
+                sat = true;
+                return;
+            }
+            for_rewritten_blocks(g, beta, nblocks, [&](uint64_t k) { lb.set(k); });
+        };
+        while (!sat && (i < a.size() || j < b.size())) {
             if (j == b.size() || (i < a.size() && a[i].first < b[j].first)) add(*a[i++].second);
             else if (i == a.size() || b[j].first < a[i].first) add(*b[j++].second);
             else { ++i; ++j; }
         }
-        bool sat = lb.all();
+        sat = sat || lb.all();
         for (size_t s = s_edit; s < nseg && !sat; ++s)
             for (const auto &p : plans_[s]->passes) {
                 for_pass_actions(p, beta, [&](const BlockAction &ba) {
@@ -369,7 +392,7 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     auto seq_hash = [&](const std::vector<PPass> &passes) {
         std::vector<uint64_t> h(nblocks, 0);
         auto mix = [&](uint64_t j, uint64_t v) { h[j] = hash_mix(h[j], v); };
-        for (const auto &p : passes)
+        for (const auto &p : passes) {
             for (const auto &stg : p.stages) {
                 if (!stg.U.empty()) {
                     uint64_t id = 1469598103934665603ull;
@@ -385,6 +408,15 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
                     for_rewritten_blocks(g, beta, nblocks, [&](uint64_t j) { mix(j, id); });
                 }
             }
+            // a store permutation moves every amplitude of the tile's
+            // positions: it counts as rewriting every block
+            if (p.relabels()) {
+                uint64_t id = hash_mix(0x52454c4142454cull, p.qlist.size());
+                for (size_t k = 0; k < p.qlist.size(); ++k)
+                    id = hash_mix(hash_mix(id, uint64_t(p.qlist[k])), uint64_t(p.out_pos(int(k))));
+                for (uint64_t j = 0; j < nblocks; ++j) mix(j, id);
+            }
+        }
         return h;
     };
     const std::vector<uint64_t> ho = seq_hash(op), hn = seq_hash(np);
@@ -414,9 +446,16 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
     return QTASK_OK;
 }
 
-int Session::prepare(bool force_full) {
+// Host-only part of an update: segments, plans (kept on the host until the
+// commit uploads them), the restart point, the closed-set decision and its
+// tile lists, and the device bytes the session will hold after the commit.
+// Nothing on the device changes here, so a failure (or a caller that decides
+// not to commit) leaves the previous result and its checkpoints as they were.
+int Session::plan_update(bool force_full) {
     const double t0 = now_ms();
     prep_t0_ = t0;
+    prep_pending_ = false;
+    prep_committed_ = false;
     launches.clear();
     qtask_stats st{};
     st.struct_size = sizeof(st);
@@ -425,6 +464,8 @@ int Session::prepare(bool force_full) {
     st.total_blocks = uint64_t(1) << (n_int - std::min(opts.block_bits, n_int));
     prep_mode_ = 0;
     prep_tiles_.clear();
+    prep_list_off_.clear();
+    prep_need_bytes_ = device_bytes();
 
     PlanParams pp;
     pp.n = n_int;
@@ -434,6 +475,7 @@ int Session::prepare(bool force_full) {
     pp.fusion = opts.fusion;
     pp.fuse_k = opts.fuse_width;
     pp.swz = dtype == QTASK_C128 ? 4 : 5;
+    pp.relabel = opts.relabel;
 
     const bool full = force_full || !have_result_;
     if (!full && !circ.edited()) {
@@ -475,20 +517,13 @@ int Session::prepare(bool force_full) {
             futs.push_back(std::async(i + 1 < i1 ? std::launch::async : std::launch::deferred,
                                       [&pp, &td = todo[i]] { return plan_segment(td.second, pp, td.first); }));
         for (size_t i = i0; i < i1; ++i) {
-            SegmentPlan np;
             try {
-                np = futs[i - i0].get();
+                plan_cache_.emplace(todo[i].first, futs[i - i0].get());
             } catch (const std::exception &e) {
                 for (size_t j = i + 1; j < i1; ++j) futs[j - i0].wait();  // no thread outlives its inputs
                 last_error = e.what();
                 return QTASK_E_ARG;
             }
-            int rc = upload_plan(np);
-            if (rc != QTASK_OK) {
-                for (size_t j = i + 1; j < i1; ++j) futs[j - i0].wait();
-                return rc;
-            }
-            plan_cache_.emplace(todo[i].first, std::move(np));
         }
     }
     for (size_t s = 0; s < S; ++s) plans_[s] = &plan_cache_.at(segs_[s].hash);
@@ -509,52 +544,8 @@ int Session::prepare(bool force_full) {
             }
         }
     }
-
-    // memory: state, checkpoints of the stored boundaries, scalars
-    for (auto it = ckpts_.begin(); it != ckpts_.end();) {
-        bool keep = false;
-        for (size_t j = 1; j < S; ++j)
-            if (segs_[j - 1].anchor == it->first && stores_ckpt(j, S)) keep = true;
-        if (!keep) {
-            dfree(it->second.buf.p);
-            it = ckpts_.erase(it);
-        } else {
-            ++it;
-        }
-    }
-    for (size_t j = 1; j < S; ++j) {
-        if (!stores_ckpt(j, S)) continue;
-        Ckpt &ck = ckpts_[segs_[j - 1].anchor];
-        if (!plan_only && !ck.buf.p) {
-            ck.buf.p = dalloc(state_bytes());
-            if (!ck.buf.p) {
-                ckpts_.erase(segs_[j - 1].anchor);
-                return QTASK_E_NOMEM;
-            }
-            ck.buf.bytes = state_bytes();
-            ck.valid = false;
-        }
-    }
     for (size_t j = 1; j < S; ++j) (void)slot_of(segs_[j - 1].anchor);
-    if (!plan_only) {
-        int rc = ensure_state();
-        if (rc != QTASK_OK) return rc;
-        rc = ensure_scalars(next_slot_ + 1);
-        if (rc != QTASK_OK) return rc;
-        const uint64_t max_tiles = uint64_t(1) << (n_int - pp.b);
-        const size_t need = std::max<size_t>(max_tiles, 4096);
-        if (partials_cap_ < need) {
-            dfree(d_partials_);
-            d_partials_ = static_cast<double *>(dalloc(need * sizeof(double)));
-            if (!d_partials_) { partials_cap_ = 0; return QTASK_E_NOMEM; }
-            partials_cap_ = need;
-        }
-        if (!d_u64_) {
-            d_u64_ = static_cast<unsigned long long *>(dalloc(4096 * sizeof(unsigned long long)));
-            if (!d_u64_) return QTASK_E_NOMEM;
-            u64_cap_ = 4096;
-        }
-    }
+
     const bool renorm = dtype == QTASK_C64 && opts.renorm != 0;
     prep_renorm_ = renorm;
     int mode = full ? 1 : 2;
@@ -572,7 +563,6 @@ int Session::prepare(bool force_full) {
     if (mode == 3) prep_set_ = set;
 
     // tile lists for the closed replay
-    std::vector<size_t> list_off;
     if (mode == 3) {
         const int beta = std::min(opts.block_bits, n_int);
         const std::vector<uint32_t> blocks = set.list();
@@ -596,38 +586,225 @@ int Session::prepare(bool force_full) {
                         tl.push_back(uint32_t(pext_tile((uint64_t(blk) << beta) | lo, kp.nonq_pos, kp.n_nonq)));
                 std::sort(tl.begin(), tl.end());
                 tl.erase(std::unique(tl.begin(), tl.end()), tl.end());
-                list_off.push_back(prep_tiles_.size());
+                prep_list_off_.push_back(prep_tiles_.size());
                 prep_tiles_.insert(prep_tiles_.end(), tl.begin(), tl.end());
             }
-        list_off.push_back(prep_tiles_.size());
-        if (!plan_only) {
-            if (tiles_cap_ < prep_tiles_.size()) {
-                dfree(d_tiles_);
-                const size_t cap = prep_tiles_.size() + 4096;
-                d_tiles_ = static_cast<uint32_t *>(dalloc(cap * sizeof(uint32_t)));
-                if (!d_tiles_) { tiles_cap_ = 0; return QTASK_E_NOMEM; }
-                tiles_cap_ = cap;
+        prep_list_off_.push_back(prep_tiles_.size());
+    }
+    st.plan_ms = now_ms() - t0;
+    last = st;
+    prep_need_bytes_ = bytes_after_commit();
+    prep_pending_ = true;
+    return QTASK_OK;
+}
+
+// Sizes the commit grows the scratch buffers to (0: no growth needed).
+Session::ScratchNeed Session::scratch_need() const {
+    ScratchNeed z;
+    const int b = std::min(opts.tile_bits, n_int);
+    const size_t slots = next_slot_ + 1;
+    if (scalars_cap_ / 2 < slots) z.scalars = 2 * std::max<size_t>(2 * slots, 64);
+    const size_t np = std::max<size_t>(size_t(1) << (n_int - b), 4096);
+    if (partials_cap_ < np) z.partials = np;
+    if (!d_u64_ || u64_cap_ < 4096) z.u64 = 4096;
+    if (prep_mode_ == 3) {
+        if (tiles_cap_ < prep_tiles_.size()) z.tiles = prep_tiles_.size() + 4096;
+        const size_t words = prep_set_.words().size();
+        if (mask_cap_ < words) z.mask = words;
+    }
+    return z;
+}
+
+// Device bytes the session holds once the pending commit is done: the
+// state, one buffer per stored checkpoint, the blobs of the plans in use and
+// the scratch buffers (grown where the commit grows them).
+uint64_t Session::bytes_after_commit() const {
+    if (plan_only) return 0;
+    if (!prep_pending_) return device_bytes();  // nothing planned: the commit changes nothing
+    const size_t S = segs_.size();
+    uint64_t b = state_bytes();
+    for (size_t j = 1; j < S; ++j)
+        if (stores_ckpt(j, S)) b += state_bytes();
+    std::unordered_set<uint64_t> live;
+    for (const auto &sg : segs_)
+        if (live.insert(sg.hash).second) b += plan_cache_.at(sg.hash).blob.size();
+    const ScratchNeed z = scratch_need();
+    b += (z.scalars ? z.scalars : scalars_cap_) * sizeof(double);
+    b += (z.partials ? z.partials : partials_cap_) * sizeof(double);
+    b += (z.u64 ? z.u64 : u64_cap_) * sizeof(unsigned long long);
+    b += (z.tiles ? z.tiles : tiles_cap_) * sizeof(uint32_t);
+    b += (z.mask ? z.mask : mask_cap_) * sizeof(uint64_t);
+    return b;
+}
+
+// Device part of an update: allocate everything the planned replay needs
+// first (plan blobs, checkpoint buffers, state, scratch), and only when all
+// of it succeeded change the session's buffers, upload and build the launch
+// list.  QTASK_E_NOMEM therefore leaves the previous result, its
+// checkpoints and their validity untouched.
+int Session::commit_device() {
+    if (!prep_pending_) return QTASK_OK;
+    if (prep_mode_ == 0) {
+        prep_pending_ = false;
+        return QTASK_OK;
+    }
+    const size_t S = prep_S_;
+    const size_t s0 = prep_s0_;
+    const int mode = prep_mode_;
+    const bool renorm = prep_renorm_;
+    qtask_stats &st = last;
+
+    // --- 1. allocations (nothing of the session changes yet)
+    std::vector<void *> fresh;
+    auto undo = [&] {
+        for (void *p : fresh) dfree(p);
+        return QTASK_E_NOMEM;
+    };
+    auto grab = [&](size_t bytes) {
+        void *p = dalloc(bytes);
+        if (p) fresh.push_back(p);
+        return p;
+    };
+    std::vector<std::pair<SegmentPlan *, void *>> plan_bufs;
+    std::vector<uint64_t> need_ckpt;   // stored boundaries without a buffer
+    std::vector<uint64_t> spare_ckpt;  // buffers of boundaries no longer stored
+    std::vector<void *> new_ckpt;
+    void *new_state = nullptr;
+    double *new_scalars = nullptr, *new_partials = nullptr;
+    unsigned long long *new_u64 = nullptr;
+    uint32_t *new_tiles = nullptr;
+    uint64_t *new_mask = nullptr;
+    const ScratchNeed z = scratch_need();
+    if (!plan_only) {
+        std::unordered_set<uint64_t> seen;
+        for (const auto &sg : segs_) {
+            SegmentPlan &sp = plan_cache_.at(sg.hash);
+            if (sp.dev || !seen.insert(sg.hash).second) continue;
+            void *p = grab(sp.blob.size());
+            if (!p) return undo();
+            plan_bufs.emplace_back(&sp, p);
+        }
+        std::unordered_set<uint64_t> stored;
+        for (size_t j = 1; j < S; ++j)
+            if (stores_ckpt(j, S)) stored.insert(segs_[j - 1].anchor);
+        for (uint64_t a : stored) {
+            auto it = ckpts_.find(a);
+            if (it == ckpts_.end() || !it->second.buf.p) need_ckpt.push_back(a);
+        }
+        for (const auto &kv : ckpts_)
+            if (!stored.count(kv.first) && kv.second.buf.p) spare_ckpt.push_back(kv.first);
+        for (size_t i = spare_ckpt.size(); i < need_ckpt.size(); ++i) {
+            void *p = grab(state_bytes());
+            if (!p) return undo();
+            new_ckpt.push_back(p);
+        }
+        if (!state_.p && !(new_state = grab(state_bytes()))) return undo();
+        if (z.scalars && !(new_scalars = static_cast<double *>(grab(z.scalars * sizeof(double))))) return undo();
+        if (z.partials && !(new_partials = static_cast<double *>(grab(z.partials * sizeof(double))))) return undo();
+        if (z.u64 && !(new_u64 = static_cast<unsigned long long *>(grab(z.u64 * sizeof(unsigned long long)))))
+            return undo();
+        if (z.tiles && !(new_tiles = static_cast<uint32_t *>(grab(z.tiles * sizeof(uint32_t))))) return undo();
+        if (z.mask && !(new_mask = static_cast<uint64_t *>(grab(z.mask * sizeof(uint64_t))))) return undo();
+    }
+
+    // --- 2. commit: from here on only device errors can fail
+    prep_pending_ = false;
+    prep_committed_ = true;
+    if (!plan_only) {
+        for (auto &pb : plan_bufs) {
+            pb.first->dev = pb.second;
+            pb.first->dev_bytes = pb.first->blob.size();
+            HIPCHK(hipMemcpyAsync(pb.second, pb.first->blob.data(), pb.first->blob.size(), hipMemcpyHostToDevice,
+                                  stream));
+        }
+        size_t nspare = 0, nfresh = 0;
+        for (uint64_t a : need_ckpt) {
+            Ckpt &ck = ckpts_[a];
+            if (nspare < spare_ckpt.size()) {
+                Ckpt &old = ckpts_.at(spare_ckpt[nspare++]);
+                ck.buf = old.buf;
+                old.buf = DevBuf{};
+            } else {
+                ck.buf.p = new_ckpt[nfresh++];
+                ck.buf.bytes = state_bytes();
             }
-            const auto &w = set.words();
-            if (mask_cap_ < w.size()) {
-                dfree(d_mask_);
-                d_mask_ = static_cast<uint64_t *>(dalloc(w.size() * sizeof(uint64_t)));
-                if (!d_mask_) { mask_cap_ = 0; return QTASK_E_NOMEM; }
-                mask_cap_ = w.size();
+            ck.valid = false;
+        }
+        for (auto it = ckpts_.begin(); it != ckpts_.end();) {
+            bool keep = false;
+            for (size_t j = 1; j < S && !keep; ++j)
+                keep = segs_[j - 1].anchor == it->first && stores_ckpt(j, S);
+            if (!keep) {
+                dfree(it->second.buf.p);
+                it = ckpts_.erase(it);
+            } else {
+                ++it;
             }
+        }
+        if (new_state) {
+            state_.p = new_state;
+            state_.bytes = state_bytes();
+        }
+        if (new_scalars) {
+            const size_t half = z.scalars / 2;
+            if (d_scalars_) {
+                // keep the norms and scales of still-valid checkpoints
+                const size_t old = scalars_cap_ / 2;
+                HIPCHK(hipMemcpyAsync(new_scalars, d_scalars_, old * sizeof(double), hipMemcpyDeviceToDevice, stream));
+                HIPCHK(hipMemcpyAsync(new_scalars + half, d_scalars_ + old, old * sizeof(double),
+                                      hipMemcpyDeviceToDevice, stream));
+                HIPCHK(hipStreamSynchronize(stream));
+                dfree(d_scalars_);
+            }
+            d_scalars_ = new_scalars;
+            scalars_cap_ = z.scalars;
+        }
+        if (new_partials) {
+            dfree(d_partials_);
+            d_partials_ = new_partials;
+            partials_cap_ = z.partials;
+        }
+        if (new_u64) {
+            dfree(d_u64_);
+            d_u64_ = new_u64;
+            u64_cap_ = z.u64;
+        }
+        if (new_tiles) {
+            dfree(d_tiles_);
+            d_tiles_ = new_tiles;
+            tiles_cap_ = z.tiles;
+        }
+        if (new_mask) {
+            dfree(d_mask_);
+            d_mask_ = new_mask;
+            mask_cap_ = z.mask;
+        }
+        if (mode == 3) {
             if (!prep_tiles_.empty())
                 HIPCHK(hipMemcpyAsync(d_tiles_, prep_tiles_.data(), prep_tiles_.size() * sizeof(uint32_t),
                                       hipMemcpyHostToDevice, stream));
+            const auto &w = prep_set_.words();
             HIPCHK(hipMemcpyAsync(d_mask_, w.data(), w.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream));
             // pageable copies: make sure they completed before the host vectors change
             HIPCHK(hipStreamSynchronize(stream));
         }
+    } else {
+        // plan-only sessions keep a record per stored boundary (no buffers)
+        for (auto it = ckpts_.begin(); it != ckpts_.end();) {
+            bool keep = false;
+            for (size_t j = 1; j < S && !keep; ++j)
+                keep = segs_[j - 1].anchor == it->first && stores_ckpt(j, S);
+            it = keep ? std::next(it) : ckpts_.erase(it);
+        }
+        for (size_t j = 1; j < S; ++j)
+            if (stores_ckpt(j, S)) (void)ckpts_[segs_[j - 1].anchor];
     }
 
     // launch list
     size_t li = 0;
     double bytes = 0, flops = 0, mfma_flops = 0;
     double *scales = plan_only ? nullptr : d_scalars_ + scalars_cap_ / 2;
+    st.passes = st.stages = st.tiles = st.gate_amp_updates = 0;
     for (size_t s = s0; s < S; ++s) {
         const SegmentPlan &sp = *plans_[s];
         const int b = sp.pp.b;
@@ -659,8 +836,8 @@ int Session::prepare(bool force_full) {
             a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
             uint64_t tiles = full_tiles;
             if (mode == 3) {
-                tiles = list_off[li + 1] - list_off[li];
-                a.tile_list = d_tiles_ ? d_tiles_ + list_off[li] : nullptr;
+                tiles = prep_list_off_[li + 1] - prep_list_off_[li];
+                a.tile_list = d_tiles_ ? d_tiles_ + prep_list_off_[li] : nullptr;
                 a.store_mask = d_mask_;
             }
             L.n_tiles = uint32_t(tiles);
@@ -704,9 +881,14 @@ int Session::prepare(bool force_full) {
         for (auto it = key_hash_.begin(); it != key_hash_.end();)
             it = live.count(it->second) ? std::next(it) : key_hash_.erase(it);
     }
-    st.plan_ms = now_ms() - t0;
-    last = st;
+    st.plan_ms = now_ms() - prep_t0_;
     return QTASK_OK;
+}
+
+int Session::prepare(bool force_full) {
+    int rc = plan_update(force_full);
+    if (rc != QTASK_OK) return rc;
+    return commit_device();
 }
 
 int Session::enqueue_after(const Launch &L, hipStream_t s) {
@@ -738,7 +920,8 @@ int Session::enqueue_prepared(hipStream_t s) {
 }
 
 int Session::finish_prepared_host() {
-    if (prep_mode_ == 0) return QTASK_OK;
+    if (prep_mode_ == 0 || !prep_committed_) return QTASK_OK;
+    prep_committed_ = false;
     const size_t S = prep_S_;
     for (size_t j = 1; j < S; ++j) {
         auto it = ckpts_.find(segs_[j - 1].anchor);
@@ -780,12 +963,10 @@ int Session::update(bool force_full) {
     if (rc != QTASK_OK) return rc;
     rc = ensure_tuned();
     if (rc != QTASK_OK) return rc;
-    rc = prepare(force_full);
-    if (rc != QTASK_OK) {
-        state_valid_ = false;
-        have_result_ = false;
-        return rc;
-    }
+    rc = plan_update(force_full);
+    if (rc == QTASK_OK) rc = commit_device();
+    if (rc == QTASK_E_DEVICE) invalidate();
+    if (rc != QTASK_OK) return rc;  // planning and allocation failures keep the previous result
     if (prep_mode_ == 0) {
         last.wall_ms = now_ms() - t0;
         return QTASK_OK;
@@ -842,7 +1023,7 @@ void Session::release_device() {
 
 int Session::read(uint64_t first, uint64_t count, void *out) {
     if (plan_only) return QTASK_E_UNSUPPORTED;
-    if (!state_valid_ || circ.edited()) return QTASK_E_STALE;
+    if (!state_valid_ || !state_.p || circ.edited()) return QTASK_E_STALE;
     const uint64_t N = uint64_t(1) << n;
     if (first > N || count > N - first) return QTASK_E_NOTFOUND;
     if (count == 0) return QTASK_OK;
@@ -856,7 +1037,7 @@ int Session::read(uint64_t first, uint64_t count, void *out) {
 
 int Session::norm(double *out) {
     if (plan_only) return QTASK_E_UNSUPPORTED;
-    if (!state_valid_ || circ.edited()) return QTASK_E_STALE;
+    if (!state_valid_ || !state_.p || circ.edited()) return QTASK_E_STALE;
     HIPCHK(hipSetDevice(opts.device));
     const uint64_t N = uint64_t(1) << n_int;
     HIPCHK(launch_norm(dtype, state_.p, N, d_partials_, reinterpret_cast<double *>(d_u64_), nullptr, stream));
@@ -869,7 +1050,7 @@ int Session::norm(double *out) {
 
 int Session::hash(uint64_t *out) {
     if (plan_only) return QTASK_E_UNSUPPORTED;
-    if (!state_valid_ || circ.edited()) return QTASK_E_STALE;
+    if (!state_valid_ || !state_.p || circ.edited()) return QTASK_E_STALE;
     HIPCHK(hipSetDevice(opts.device));
     const uint64_t N = uint64_t(1) << n_int;
     HIPCHK(launch_hash(dtype, state_.p, N, d_u64_ + 1, d_u64_, stream));

@@ -58,8 +58,27 @@ public:
     // checkpoints, plans); used for admission
     uint64_t planned_bytes() const;
 
-    // --- used by the server's batched small-session path
-    int prepare(bool force_full);           // plan + decide the replay (no launches)
+    // --- an update in two phases (also used by the server): plan_update()
+    // runs on the host only (segments, plans, restart point, closed-set
+    // decision) and leaves the device untouched; commit_device() allocates
+    // everything the replay needs before it changes any buffer, then uploads
+    // and builds the launch list.  A failure in either keeps the previous
+    // result and its checkpoints.
+    int plan_update(bool force_full);
+    int commit_device();
+    // device bytes held after the pending commit (valid after plan_update)
+    uint64_t bytes_after_commit() const;
+    // the circuit (and its segment cut) before a batch of modifiers, so that
+    // a request whose edits or update fail can be undone as a whole
+    void save_edit_point() { saved_circ_ = circ; saved_anchors_ = anchors_; }
+    void rollback_edit_point() {
+        circ = saved_circ_;
+        anchors_ = saved_anchors_;
+        prep_pending_ = false;
+        prep_committed_ = false;
+        launches.clear();
+    }
+    int prepare(bool force_full);           // plan_update + commit_device (no launches)
     struct Launch {                          // one pass launch of the prepared replay
         KArgs args;
         uint32_t n_tiles;
@@ -76,6 +95,10 @@ public:
     // free every device buffer (state, checkpoints, plans, scratch); the next
     // update re-simulates from scratch
     void release_device();
+    void release_state() {
+        dfree(state_.p);
+        state_ = DevBuf{};
+    }
     // where the renormalisation sum of a launch with after == 1 goes
     void sum_targets(const Launch &l, const double **partials, double **norm, double **scale) const {
         *partials = d_partials_;
@@ -86,7 +109,7 @@ public:
     bool needs_final() const { return prep_S_ == 0 || (prep_renorm_ && prep_mode_ != 0); }
 
     void *state() const { return state_.p; }
-    bool state_valid() const { return state_valid_; }
+    bool state_valid() const { return state_valid_ && state_.p != nullptr; }
     qtask_stats last{};
     std::string last_error;
 
@@ -115,7 +138,6 @@ private:
     void build_segments(const PlanParams &pp);
     size_t slot_of(uint64_t anchor);
     int ensure_state();
-    int ensure_scalars(size_t slots);
     int upload_plan(SegmentPlan &sp);
     int try_closed(size_t s0, size_t s_edit, BlockSet &S);
 
@@ -127,6 +149,8 @@ private:
     std::vector<uint64_t> prev_hashes_;                   // segment hashes at the last update
     std::vector<uint64_t> prev_anchors_;                  // segment end anchors at the last update
     std::unordered_set<uint64_t> anchors_;
+    Circuit saved_circ_{0};
+    std::unordered_set<uint64_t> saved_anchors_;
     std::unordered_map<uint64_t, Ckpt> ckpts_;            // by anchor level id
     std::unordered_map<uint64_t, size_t> slots_;          // anchor -> norm/scale slot (0: circuit end)
     size_t next_slot_ = 1;
@@ -143,7 +167,17 @@ private:
     bool dev_ready_ = false;
     bool tuned_ = false;
 
+    // sizes the commit grows the scratch buffers to (0: unchanged)
+    struct ScratchNeed {
+        size_t scalars = 0, partials = 0, u64 = 0, tiles = 0, mask = 0;
+    };
+    ScratchNeed scratch_need() const;
+
     // prepared replay
+    bool prep_pending_ = false;             // planned, not committed yet
+    bool prep_committed_ = false;           // committed: the launch list is the current replay
+    uint64_t prep_need_bytes_ = 0;
+    std::vector<size_t> prep_list_off_;     // closed replay: tile-list offset per pass launch
     size_t prep_s0_ = 0, prep_S_ = 0, prep_first_edit_ = 0;
     int prep_mode_ = 0;
     bool prep_renorm_ = false;

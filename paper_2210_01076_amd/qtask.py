@@ -40,7 +40,7 @@ class qtask_opts(ctypes.Structure):
                 ("block_bits", i32), ("fusion", i32), ("fuse_width", i32), ("ckpt_interval", i32),
                 ("max_ckpts", i32), ("renorm", i32), ("autotune", i32), ("closed_mode", i32),
                 ("stream", ctypes.c_void_p), ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p),
-                ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc_ctx", ctypes.c_void_p), ("relabel", i32)]
 
 
 class qtask_stats(ctypes.Structure):
@@ -114,6 +114,7 @@ _SIGS = {
     "qtask_server_drain": ([vp], ctypes.c_int),
     "qtask_server_session": ([vp, i32, P(vp)], ctypes.c_int),
     "qtask_server_usage": ([vp, P(u64), P(i32)], ctypes.c_int),
+    "qtask_server_peak_bytes": ([vp, P(u64)], ctypes.c_int),
 }
 
 _lib = None
@@ -389,15 +390,87 @@ def qtask_server_usage(s):
     return b.value, r.value
 
 
+def qtask_server_peak_bytes(s) -> int:
+    b = u64()
+    check(load().qtask_server_peak_bytes(s, ctypes.byref(b)), "qtask_server_peak_bytes")
+    return b.value
+
+
 # ------------------------------------------------------------- convenience
 
-class Simulator:
-    """A session built from nets of ``(kind, qubits, params)`` tuples."""
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
-    def __init__(self, n: int, dtype: str = "c128", **opts):
+
+class DeviceAllocator:
+    """The ``alloc``/``free`` hooks of ``qtask_opts`` backed by Python
+    callables: ``alloc(nbytes) -> int`` (a device pointer, 0 on failure)
+    and ``free(ptr)``.  Keep the object alive as long as the session."""
+
+    def __init__(self, alloc, free):
+        self._alloc, self._free = alloc, free
+        self.c_alloc = ALLOC_FN(lambda nbytes, ctx: self._alloc(int(nbytes)) or None)
+        self.c_free = FREE_FN(lambda ptr, ctx: self._free(int(ptr)) if ptr else None)
+
+    def install(self, o: qtask_opts) -> None:
+        o.alloc = ctypes.cast(self.c_alloc, ctypes.c_void_p)
+        o.free = ctypes.cast(self.c_free, ctypes.c_void_p)
+        o.alloc_ctx = None
+
+
+def _runtime_lib() -> ctypes.CDLL:
+    """The HIP runtime libqtask.so is linked against (found through the
+    process's mappings, so it is the same copy, not another one)."""
+    load()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                return ctypes.CDLL(line.split()[-1])
+    raise RuntimeError("the HIP runtime of libqtask.so is not mapped")
+
+
+def hip_allocator(on_alloc=None, on_free=None) -> DeviceAllocator:
+    """Hooks that allocate with hipMalloc/hipFree of the library's own HIP
+    runtime.  ``on_alloc(nbytes)`` may return False to refuse an allocation
+    (the hook then returns NULL, as an exhausted allocator would);
+    ``on_free(ptr)`` observes frees.  Memory from another runtime in the
+    process (torch's wheel bundles its own HIP runtime) is not usable here:
+    the library's runtime does not know its pointers."""
+    rt = _runtime_lib()
+    rt.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    rt.hipMalloc.restype = ctypes.c_int
+    rt.hipFree.argtypes = [ctypes.c_void_p]
+    rt.hipFree.restype = ctypes.c_int
+
+    def alloc(nbytes):
+        if on_alloc is not None and on_alloc(nbytes) is False:
+            return 0
+        p = ctypes.c_void_p()
+        if rt.hipMalloc(ctypes.byref(p), nbytes) != 0:
+            return 0
+        return p.value or 0
+
+    def free(ptr):
+        if on_free is not None:
+            on_free(ptr)
+        rt.hipFree(ptr)
+
+    return DeviceAllocator(alloc, free)
+
+
+class Simulator:
+    """A session built from nets of ``(kind, qubits, params)`` tuples.
+    ``allocator`` is None (the library calls hipMalloc itself) or a
+    ``DeviceAllocator`` whose hooks the library calls instead."""
+
+    def __init__(self, n: int, dtype: str = "c128", allocator=None, **opts):
         self.n = n
         self.dtype = QTASK_C128 if dtype in ("c128", QTASK_C128) else QTASK_C64
+        self.h = None
         o = qtask_opts_default(**opts)
+        self.allocator = allocator
+        if allocator is not None:
+            allocator.install(o)
         self.h = qtask_create(n, self.dtype, o)
         self.levels: List[int] = []          # level ids in circuit order
         self.gates: List[List[int]] = []     # gate ids per level, insertion order

@@ -260,18 +260,20 @@ def modifier_batches(n: int, nets: List[Net], seed: int, batches: int,
 
 
 def split_edits(n: int, nets: List[Net], seed: int, count: int, b: int,
-                kinds: Sequence[str] = ("rx", "ry", "rz", "cp")) -> List[List[Edit]]:
+                kinds: Sequence[str] = ("rx", "ry", "rz", "cp"), tail: int = 0) -> List[List[Edit]]:
     """``count`` single-gate inserts at uniform nets, alternating between
     gates whose qubits all lie below ``b`` (inside one tile) and gates with a
     qubit at or above ``b``.  The qubits come from the net's free qubits when
     enough are free; otherwise the gate goes into a new net right after it.
+    With ``tail`` > 0 the nets are drawn among the last ``tail`` nets only.
     Drawn against a private copy of the circuit, like modifier_batches."""
     rng = np.random.default_rng(seed)
     model = [list(net) for net in nets]
     out: List[List[Edit]] = []
     for i in range(count):
         high = i % 2 == 1
-        li = int(rng.integers(len(model)))
+        lo = max(0, len(model) - tail) if tail > 0 else 0
+        li = int(rng.integers(lo, len(model)))
         kind = str(kinds[int(rng.integers(len(kinds)))])
         k = N_QUBITS[kind]
         free = _free_qubits(n, model[li])
@@ -312,7 +314,7 @@ class Workload:
     n: int
     nets: List[Net]
     batches: List[List[Edit]] = field(default_factory=list)
-    ckpt_levels: int = 0  # nets per checkpoint segment (0 = library default)
+    ckpt_nets: int = 0  # nets per checkpoint segment (0 = library default); 50 levels in every family
 
 
 def config(cfg: int, *, levels: int = None, n: int = None, batches: int = None) -> Workload:
@@ -330,19 +332,19 @@ def config(cfg: int, *, levels: int = None, n: int = None, batches: int = None) 
         nets = layered_circuit(n, levels or 200, seed_for(2))
         b = modifier_batches(n, nets, seed_for(2, "modifier"), batches or 100, 1, 4,
                              LAYERED_EDIT_KINDS)
-        return Workload("layered_n%d_l%d" % (n, levels or 200), n, nets, b, ckpt_levels=50)
+        return Workload("layered_n%d_l%d" % (n, levels or 200), n, nets, b, ckpt_nets=100)
     if cfg == 3:
         n = n or 30
         nets = layered_circuit(n, levels or 300, seed_for(3))
         b = modifier_batches(n, nets, seed_for(3, "modifier"), batches or 0, 1, 4,
                              LAYERED_EDIT_KINDS) if batches else []
-        return Workload("layered_n%d_l%d" % (n, levels or 300), n, nets, b, ckpt_levels=100)
+        return Workload("layered_n%d_l%d" % (n, levels or 300), n, nets, b, ckpt_nets=100)
     if cfg == 5:
         n = n or 32
         nets = cp_ladder_circuit(n, levels or 500, seed_for(5))
         b = modifier_batches(n, nets, seed_for(5, "modifier"), batches or 50, 1, 1,
                              ("rx", "ry", "rz", "cp"))
-        return Workload("cp_ladder_n%d_l%d" % (n, levels or 500), n, nets, b, ckpt_levels=150)
+        return Workload("cp_ladder_n%d_l%d" % (n, levels or 500), n, nets, b, ckpt_nets=150)
     raise ValueError("configuration %d is a serving workload; use serving_sessions()" % cfg)
 
 

@@ -1,0 +1,163 @@
+"""Failure injection from the host: a device allocator that fails, through
+the allocator hooks of qtask_opts.  An update that runs out of memory must
+leave the previous result and its checkpoints in place (the header's error
+contract), and the update after it must resume from them."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2210_01076_amd import qtask as Q
+from paper_2210_01076_amd import workloads as W
+from tests.gpu_util import bytes_equal, check_state, log
+
+pytestmark = pytest.mark.gpu
+
+
+class FailingAllocator:
+    """hipMalloc of the library's own HIP runtime that returns NULL for the
+    allocations numbered fail_from, fail_from + 1, ... (counted from 0)
+    while armed; it records which pointers are live."""
+
+    def __init__(self):
+        self.calls = 0
+        self.fail_from = None
+        self.failed = 0
+        self.live = {}
+        self.pending = None
+        inner = Q.hip_allocator()
+
+        def alloc(nbytes):
+            k = self.calls
+            self.calls += 1
+            if self.fail_from is not None and k >= self.fail_from:
+                self.failed += 1
+                return 0
+            p = inner._alloc(nbytes)
+            if p:
+                self.live[p] = nbytes
+            return p
+
+        def free(ptr):
+            assert ptr in self.live, "free of a pointer the allocator did not hand out"
+            del self.live[ptr]
+            inner._free(ptr)
+
+        self.hooks = Q.DeviceAllocator(alloc, free)
+
+
+def _append(s, nets, extra):
+    for net in extra:
+        li = len(s.levels)
+        s.add_level(li)
+        for g in net:
+            s.add_gate(li, g)
+        nets.append(list(net))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("fail_at", [0, 1, 2, 3])
+def test_nomem_keeps_previous_result(dtype, fail_at):
+    """n=14, 20 nets in segments of 4 (a checkpoint at every boundary); then
+    8 more nets, which need new plans and two new checkpoint buffers.  The
+    allocator fails from its fail_at-th allocation of that update on: the
+    update returns QTASK_E_NOMEM, the session's device bytes do not change,
+    and once the allocator works again the next update resumes from the
+    stored checkpoints (not from |0...0>) and matches the oracle and a full
+    re-simulation.  Undoing the appended nets instead gives back the
+    previous state bit for bit."""
+    n = 14
+    nets = W.layered_circuit(n, 10, 61)
+    more = W.layered_circuit(n, 4, 62)
+    fa = FailingAllocator()
+    s = Q.Simulator(n, dtype, allocator=fa.hooks, device=0, ckpt_interval=4)
+    try:
+        s.build(nets)
+        s.update()
+        before = s.state()
+        held = Q.qtask_device_bytes(s.h)
+        live = dict(fa.live)
+        _append(s, nets, more)
+        fa.fail_from = fa.calls + fail_at
+        with pytest.raises(Q.QtaskError) as e:
+            s.update()
+        assert e.value.code == Q.QTASK_E_NOMEM, e.value
+        assert fa.failed >= 1
+        # nothing the session held was freed or replaced, nothing leaked
+        assert Q.qtask_device_bytes(s.h) == held
+        assert fa.live == live
+        with pytest.raises(Q.QtaskError) as e2:
+            s.state(0, 4)
+        assert e2.value.code == Q.QTASK_E_STALE
+        # memory is back: the update resumes from the checkpoints
+        fa.fail_from = None
+        st = s.update()
+        assert st["mode"] in (2, 3) and st["first_level"] > 0, st
+        inc = s.state()
+        check_state(inc, oracle.simulate(n, nets), dtype)
+        s.update(full=True)
+        assert bytes_equal(inc, s.state())
+        log("nomem", dtype, fail_at, "failed allocations", fa.failed, "resumed at", st["first_level"], "mode",
+            st["mode"])
+        # fail again, then take the appended nets back out: the state is the
+        # one before them, bit for bit
+        _append(s, nets, W.layered_circuit(n, 2, 63))
+        fa.fail_from = fa.calls
+        with pytest.raises(Q.QtaskError):
+            s.update()
+        fa.fail_from = None
+        for _ in range(len(more) + 4):
+            s.remove_level(len(s.levels) - 1)
+        s.update()
+        assert bytes_equal(s.state(), before)
+    finally:
+        s.close()
+    assert fa.live == {}, "device memory left behind"
+
+
+def test_nomem_on_the_first_update_then_success():
+    """No memory at all for the first update: QTASK_E_NOMEM, nothing
+    allocated; the next update with memory simulates normally."""
+    n = 12
+    nets = W.layered_circuit(n, 6, 64)
+    fa = FailingAllocator()
+    fa.fail_from = 0
+    s = Q.Simulator(n, "c128", allocator=fa.hooks, device=0, ckpt_interval=4)
+    try:
+        s.build(nets)
+        with pytest.raises(Q.QtaskError) as e:
+            s.update()
+        assert e.value.code == Q.QTASK_E_NOMEM
+        assert fa.live == {}
+        fa.fail_from = None
+        st = s.update()
+        assert st["mode"] == 1
+        check_state(s.state(), oracle.simulate(n, nets), "c128")
+    finally:
+        s.close()
+    assert fa.live == {}
+
+
+def test_allocator_hooks_hold_every_buffer():
+    """Through the hooks the library allocates every device buffer it holds
+    (qtask_device_bytes adds up exactly what the hooks handed out) and frees
+    all of it on destroy; results match the oracle."""
+    n = 16
+    nets = W.layered_circuit(n, 12, 65)
+    fa = FailingAllocator()
+    s = Q.Simulator(n, "c128", allocator=fa.hooks, device=0, ckpt_interval=8)
+    try:
+        s.build(nets)
+        s.update()
+        assert Q.qtask_device_bytes(s.h) == sum(fa.live.values())
+        check_state(s.state(), oracle.simulate(n, nets), "c128")
+        e = W.Edit("remove", 5, pos=0)
+        W.apply_edit(nets, e)
+        s.apply_edit(e)
+        s.update()
+        assert Q.qtask_device_bytes(s.h) == sum(fa.live.values())
+        check_state(s.state(), oracle.simulate(n, nets), "c128")
+    finally:
+        s.close()
+    assert fa.live == {}

@@ -164,13 +164,13 @@ def test_dense_fusion_incremental_bitwise(dtype):
 
 def test_layered_24_full_size_against_oracle():
     """The 24-qubit, 200-level layered configuration in the launch setup the
-    benchmark times (autotuned tile shape, 50-net segments): the complex128
+    benchmark times (autotuned tile shape, 50-level segments): the complex128
     result equals the oracle's over the whole state; ten modifier batches
     keep incremental == full bitwise and the norm at 1; complex64 stays
     within its tolerance of complex128."""
     wl = W.config(2, batches=10)
     nets = [list(x) for x in wl.nets]
-    with sim(wl.n, nets, "c128", autotune=1, ckpt_interval=wl.ckpt_levels) as s:
+    with sim(wl.n, nets, "c128", autotune=1, ckpt_interval=wl.ckpt_nets) as s:
         s.update()
         want = oracle.simulate(wl.n, nets, nthreads=oracle.max_threads())
         err = check_state(s.state(), want, "c128", "layered-24 full")
@@ -182,7 +182,7 @@ def test_layered_24_full_size_against_oracle():
             s.update()
             _check_incremental(s, nets, wl.n, "c128", with_oracle=False)
             assert abs(s.norm() - 1.0) < 1e-12
-        with sim(wl.n, nets, "c64", autotune=1, ckpt_interval=wl.ckpt_levels) as s64:
+        with sim(wl.n, nets, "c64", autotune=1, ckpt_interval=wl.ckpt_nets) as s64:
             s64.update()
             a = s.state()
             b = s64.state().astype(np.complex128)

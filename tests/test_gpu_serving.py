@@ -165,3 +165,109 @@ def test_bad_edit_reports_status_and_session_recovers():
         assert r2["status"] == Q.QTASK_OK and r2["state_hash"] == r0["state_hash"]
     finally:
         Q.qtask_server_destroy(sv)
+
+
+def _growing_specs(seed, count, n, depth, requests, inserts):
+    """Sessions whose every request inserts new nets (each with one random
+    gate): the circuit grows, and with it the number of checkpoints."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nets = W.layered_circuit(n, depth, seed + i)
+        cur = [list(x) for x in nets]
+        reqs = []
+        for _ in range(requests):
+            batch = []
+            for _ in range(inserts):
+                li = int(rng.integers(len(cur)))
+                kind = W.LAYERED_EDIT_KINDS[int(rng.integers(len(W.LAYERED_EDIT_KINDS)))]
+                qs = tuple(int(q) for q in rng.choice(n, size=2 if kind == "cx" else 1, replace=False))
+                ps = (float(rng.uniform(0, 2 * np.pi)),) if kind in ("rx", "ry", "rz") else ()
+                e = W.Edit("insert", li, (kind, qs, ps), new_net=True)
+                W.apply_edit(cur, e)
+                batch.append(e)
+            reqs.append(batch)
+        out.append((n, "c128", nets, reqs))
+    return out
+
+
+def test_admission_holds_budget_while_sessions_grow():
+    """Requests that insert nets add segments and so checkpoints.  Admission
+    charges each session's bytes after its update (state, checkpoints, plans
+    and scratch), so under a budget of about two and a half final footprints
+    the admitted bytes never exceed the budget, even at their peak, every
+    request finishes and every result equals the session run alone."""
+    specs = _growing_specs(123, 4, 16, 6, 3, 3)
+    opts = dict(ckpt_interval=2)
+    alone = [_alone(n, d, nets, reqs, opts) for n, d, nets, reqs in specs]
+    # the largest footprint any session reaches alone
+    peak_alone = 0
+    for n, d, nets, reqs in specs[:1]:
+        nets = [list(x) for x in nets]
+        with Q.Simulator(n, d, device=0, **opts) as s:
+            s.build(nets)
+            s.update()
+            for batch in reqs:
+                for e in batch:
+                    W.apply_edit(nets, e)
+                    s.apply_edit(e)
+                s.update()
+                peak_alone = max(peak_alone, Q.qtask_device_bytes(s.h))
+    budget = int(2.5 * peak_alone)
+    sv = Q.qtask_server_create(Q.qtask_server_opts_default(budget_bytes=budget, max_inflight=4))
+    try:
+        sids, tickets, usage = [], {}, []
+        for n, dtype, nets, _ in specs:
+            sids.append(Q.qtask_server_open(sv, n, Q.QTASK_C128, Q.qtask_opts_default(device=0, **opts), nets))
+        for i, sid in enumerate(sids):
+            tickets[(i, 0)] = Q.qtask_server_submit(sv, sid, [])
+        Q.qtask_server_drain(sv)
+        usage.append(Q.qtask_server_usage(sv))
+        for r in range(3):
+            for i, sid in enumerate(sids):
+                edits = [c for e in specs[i][3][r] for c in Q.make_edits(e)]
+                tickets[(i, r + 1)] = Q.qtask_server_submit(sv, sid, edits)
+            Q.qtask_server_drain(sv)
+            usage.append(Q.qtask_server_usage(sv))
+        peak = Q.qtask_server_peak_bytes(sv)
+        for (i, r), t in sorted(tickets.items()):
+            res = Q.qtask_server_wait(sv, t, 0.0)
+            assert res["status"] == Q.QTASK_OK, (i, r, res["status"])
+            assert res["state_hash"] == alone[i][0][r], "session %d request %d" % (i, r)
+        for used, resident in usage:
+            assert used <= budget, (used, budget)
+        assert peak <= budget, (peak, budget)
+        log("growing sessions: budget", budget, "peak", peak, "usage", usage)
+    finally:
+        Q.qtask_server_destroy(sv)
+
+
+def test_request_is_undone_when_it_can_never_fit():
+    """A request whose inserted nets would need more checkpoints than the
+    budget holds fails with QTASK_E_NOMEM and is undone: the session keeps
+    its previous state and circuit, and its next request runs normally."""
+    n = 14
+    nets = W.layered_circuit(n, 4, 7)
+    opts = dict(ckpt_interval=2)
+    with Q.Simulator(n, "c128", device=0, **opts) as s:
+        s.build([list(x) for x in nets])
+        s.update()
+        fits = Q.qtask_device_bytes(s.h)
+        want = s.hash()
+    budget = fits + (1 << n) * 16 // 2   # room for less than one more checkpoint
+    sv = Q.qtask_server_create(Q.qtask_server_opts_default(budget_bytes=budget))
+    try:
+        sid = Q.qtask_server_open(sv, n, Q.QTASK_C128, Q.qtask_opts_default(device=0, **opts), nets)
+        r0 = Q.qtask_server_wait(sv, Q.qtask_server_submit(sv, sid, []), 60000.0)
+        assert r0["status"] == Q.QTASK_OK and r0["state_hash"] == want
+        grow = [Q.qtask_edit(op=2, level=len(nets) - 1) for _ in range(6)]
+        r1 = Q.qtask_server_wait(sv, Q.qtask_server_submit(sv, sid, grow), 60000.0)
+        assert r1["status"] == Q.QTASK_E_NOMEM
+        h = Q.qtask_server_session(sv, sid)
+        assert Q.qtask_num_levels(h) == len(nets)
+        assert Q.qtask_state_hash(h) == want
+        r2 = Q.qtask_server_wait(sv, Q.qtask_server_submit(sv, sid, []), 60000.0)
+        assert r2["status"] == Q.QTASK_OK and r2["state_hash"] == want
+        assert Q.qtask_server_peak_bytes(sv) <= budget
+    finally:
+        Q.qtask_server_destroy(sv)

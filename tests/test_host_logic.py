@@ -114,8 +114,38 @@ def _apply_local(psi, n, qs, m):
     return np.moveaxis(t, range(k), axes).reshape(-1)
 
 
+def _relabel(psi, n, qin, qout):
+    """Move the amplitude bit at position qin[p] to position qout[p] (a pass
+    that stores its tile with the qubits permuted)."""
+    if list(qin) == list(qout):
+        return psi
+    i = np.arange(1 << n, dtype=np.int64)
+    j = i.copy()
+    for p in qin:
+        j &= ~(np.int64(1) << p)
+    for p, o in zip(qin, qout):
+        j |= ((i >> p) & 1) << o
+    out = np.empty_like(psi)
+    out[j] = psi
+    return out
+
+
 def emulate(dump, n):
-    """Run the dumped plan of every segment on the CPU in complex128."""
+    """Run the dumped plan of every segment on the CPU in complex128: ops on
+    the positions they name, then each pass's store permutation; every
+    segment must end in the plain layout."""
+    for seg in dump["segments"]:
+        where = list(range(n))  # circuit qubit at each position
+        for ps in seg["passes"]:
+            if ps["out"] != ps["qubits"]:
+                moved = {o: where[q] for q, o in zip(ps["qubits"], ps["out"])}
+                for o, q in moved.items():
+                    where[o] = q
+        assert where == list(range(n)), "segment does not end in the plain layout"
+    return _emulate_ops(dump, n)
+
+
+def _emulate_ops(dump, n):
     psi = oracle.basis(n).astype(np.complex128)
     for seg in dump["segments"]:
         assert seg["check"] == "", seg["check"]
@@ -132,20 +162,23 @@ def emulate(dump, n):
                         m = np.array([complex(a, b) for a, b in op["m"]])
                         d = int(round(np.sqrt(m.size)))
                         psi = _apply_local(psi, n, op["q"], m.reshape(d, d))
+            psi = _relabel(psi, n, ps["qubits"], ps["out"])
     return psi
 
 
+@pytest.mark.parametrize("relabel", [0, 1])
 @pytest.mark.parametrize("n,b,c,seed,fam", [
     (5, 4, 2, 1, "dense"), (6, 5, 3, 2, "dense"), (8, 6, 4, 3, "layered"), (9, 6, 3, 4, "dense"),
-    (10, 7, 4, 5, "layered"), (10, 10, 4, 6, "dense"), (7, 4, 0, 7, "ladder")])
-def test_planner_emulation_matches_oracle(n, b, c, seed, fam):
+    (10, 7, 4, 5, "layered"), (10, 10, 4, 6, "dense"), (7, 4, 0, 7, "ladder"), (11, 7, 4, 8, "ladder"),
+    (12, 8, 5, 9, "layered")])
+def test_planner_emulation_matches_oracle(n, b, c, seed, fam, relabel):
     if fam == "dense":
         nets = W.dense_random_circuit(n, 12, seed, kinds=W.GATE_KINDS)
     elif fam == "layered":
         nets = W.layered_circuit(n, 6, seed)
     else:
         nets = W.cp_ladder_circuit(n, 5, seed)
-    with plan_only(n, tile_bits=b, low_bits=c, ckpt_interval=7) as sim:
+    with plan_only(n, tile_bits=b, low_bits=c, ckpt_interval=7, relabel=relabel) as sim:
         sim.build(nets)
         sim.update()
         dump = sim.dump()
@@ -154,6 +187,46 @@ def test_planner_emulation_matches_oracle(n, b, c, seed, fam):
     np.testing.assert_allclose(got, want, atol=1e-12)
     # every source gate lands in exactly one pass
     assert sum(seg["gates"] for seg in dump["segments"]) == W.count_gates(nets)
+    if not relabel:
+        assert all(p["out"] == p["qubits"] for seg in dump["segments"] for p in seg["passes"])
+
+
+def _passes(n, nets, **kw):
+    with plan_only(n, **kw) as sim:
+        sim.build(nets)
+        sim.update()
+        return sim.stats()["passes"], sim.dump()
+
+
+@pytest.mark.parametrize("fam,n", [("ladder", 32), ("layered", 28)])
+def test_relabelling_lets_wide_low_runs_keep_few_passes(fam, n):
+    """With relabelling, six contiguous low bits (1 KiB runs of complex128)
+    cost clearly fewer passes than without, and no more than a quarter above the
+    three-bit tiles without relabelling; every pass's store map is a
+    permutation of its tile positions, and every tile holds the low
+    positions (the emulation test above checks the arithmetic)."""
+    nets = W.cp_ladder_circuit(n, 20, 11) if fam == "ladder" else W.layered_circuit(n, 30, 12)
+    k = 150 if fam == "ladder" else 100
+    plain3, _ = _passes(n, nets, tile_bits=12, low_bits=3, ckpt_interval=k, relabel=0)
+    plain6, _ = _passes(n, nets, tile_bits=12, low_bits=6, ckpt_interval=k, relabel=0)
+    rel6, dump = _passes(n, nets, tile_bits=12, low_bits=6, ckpt_interval=k, relabel=1)
+    assert rel6 < 0.85 * plain6 and rel6 <= 1.25 * plain3, (plain3, plain6, rel6)
+    moved = 0
+    for seg in dump["segments"]:
+        for p in seg["passes"]:
+            assert sorted(p["out"]) == sorted(p["qubits"])
+            assert all(q in p["qubits"] for q in range(6))
+            moved += p["out"] != p["qubits"]
+    assert moved > 0
+
+
+def test_relabel_default_follows_state_size():
+    with plan_only(25) as s:
+        assert Q.qtask_get_opts(s.h).relabel == 0
+    with plan_only(26) as s:
+        assert Q.qtask_get_opts(s.h).relabel == 1
+    with pytest.raises(Q.QtaskError):
+        plan_only(12, relabel=2)
 
 
 def test_planner_factors_diagonal_phases():
@@ -282,15 +355,18 @@ def test_cancelling_edits_redo_nothing():
         assert st["mode"] == 3 and st["dirty_blocks"] == 0 and st["tiles"] == 0
 
 
+@pytest.mark.parametrize("relabel", [0, 1])
 @pytest.mark.parametrize("seed", range(6))
-def test_tracker_sound_against_oracle(seed):
+def test_tracker_sound_against_oracle(seed, relabel):
     """Blocks whose amplitudes actually change (at every checkpoint boundary
-    and at the end) lie inside the tracker's affected set."""
+    and at the end) lie inside the tracker's affected set (with and without
+    relabelling passes, whose store permutations move amplitude between
+    blocks)."""
     rng = np.random.default_rng(seed)
     n, bb, K = 7, 3, 2
     kinds = ("x", "cx", "ccx", "swap", "z", "s", "t", "cz", "cp", "h", "rx")
     nets = W.dense_random_circuit(n, 10, 50 + seed, kinds=("x", "cx", "z", "s", "cz", "swap", "t"))
-    with plan_only(n, block_bits=bb, ckpt_interval=K, tile_bits=5, low_bits=2) as sim:
+    with plan_only(n, block_bits=bb, ckpt_interval=K, tile_bits=5, low_bits=2, relabel=relabel) as sim:
         sim.build(nets)
         sim.update()
         for trial in range(4):
@@ -538,3 +614,158 @@ def test_server_needs_a_device():
     with pytest.raises(Q.QtaskError) as ei:
         Q.qtask_server_create(bad)
     assert ei.value.code == Q.QTASK_E_ARG
+
+
+# ------------------------------------------------- kernel-side emulation
+
+def _xor_bits(vals, idx, nbits):
+    """XOR (or OR: the contributions are disjoint) of vals[k] over the set
+    bits k of idx (vectorised over idx)."""
+    out = np.zeros_like(idx, dtype=np.int64)
+    for k in range(nbits):
+        out ^= np.where((idx >> k) & 1, np.int64(vals[k]), np.int64(0))
+    return out
+
+
+def _apply_kop(a, op, coefs):
+    """One op record on the register block a (threads x 16), as the pass
+    kernel's op switch applies it (register bits A, B, C; coefficients at
+    `coef` in the coefficient array)."""
+    ty, A, B, Cb, off = op
+    c = coefs[off:off + 512]
+    idx = np.arange(16)
+    cx = lambda k: complex(c[2 * k], c[2 * k + 1])
+    if ty == 16:  # GPH
+        a *= cx(0)
+        return
+    if ty == 11:  # DENSE
+        U = (c[0:512:2] + 1j * c[1:512:2]).reshape(16, 16)
+        a[:] = a @ U.T
+        return
+    bitA = (idx >> A) & 1
+    if ty in (12, 13, 1):  # UR, UX, U1 on pairs
+        lo = idx[bitA == 0]
+        hi = lo | (1 << A)
+        x, y = a[:, lo].copy(), a[:, hi].copy()
+        if ty == 12:
+            m = [c[0], c[1], c[2], c[3]]
+        elif ty == 13:
+            m = [c[0], 1j * c[1], 1j * c[2], c[3]]
+        else:
+            m = [cx(0), cx(1), cx(2), cx(3)]
+        a[:, lo] = m[0] * x + m[1] * y
+        a[:, hi] = m[2] * x + m[3] * y
+    elif ty == 2:  # D1
+        a[:, bitA == 0] *= cx(0)
+        a[:, bitA == 1] *= cx(1)
+    elif ty == 14:  # P1
+        a[:, bitA == 1] *= cx(0)
+    elif ty == 15:  # P2
+        a[:, (bitA == 1) & (((idx >> B) & 1) == 1)] *= cx(0)
+    elif ty in (3, 4):  # A1, X1
+        lo = idx[bitA == 0]
+        hi = lo | (1 << A)
+        x, y = a[:, lo].copy(), a[:, hi].copy()
+        if ty == 4:
+            a[:, lo], a[:, hi] = y, x
+        else:
+            a[:, lo], a[:, hi] = cx(0) * y, cx(1) * x
+    elif ty == 6:  # CX: control A, target B
+        sel = idx[(bitA == 1) & (((idx >> B) & 1) == 0)]
+        x, y = a[:, sel].copy(), a[:, sel | (1 << B)].copy()
+        a[:, sel], a[:, sel | (1 << B)] = y, x
+    elif ty == 8:  # SWAP
+        sel = idx[(bitA == 1) & (((idx >> B) & 1) == 0)]
+        oth = (sel & ~(1 << A)) | (1 << B)
+        x, y = a[:, sel].copy(), a[:, oth].copy()
+        a[:, sel], a[:, oth] = y, x
+    elif ty == 10:  # CCX: controls A, B, target C
+        sel = idx[(bitA == 1) & (((idx >> B) & 1) == 1) & (((idx >> Cb) & 1) == 0)]
+        x, y = a[:, sel].copy(), a[:, sel | (1 << Cb)].copy()
+        a[:, sel], a[:, sel | (1 << Cb)] = y, x
+    else:
+        raise AssertionError("op type %d" % ty)
+
+
+def emulate_kernel(dump, n):
+    """Run the plan blobs the way the pass kernel does, tile by tile: the
+    tile origin from the deposit runs, the first stage's registers loaded
+    through its global maps, the op records on registers, LDS exchanges
+    through the swizzled slot maps, matrix-core stages on LDS, and the last
+    stage's registers stored through its own global maps.  Every load and
+    store address is checked to lie inside the state, and every state slot
+    to be written exactly once per pass."""
+    psi = oracle.basis(n).astype(np.complex128)
+    for seg in dump["segments"]:
+        b = seg["b"]
+        coefs = np.array(seg["coefs"], dtype=np.float64)
+        nthr = 1 << (b - 4)
+        t = np.arange(nthr, dtype=np.int64)[:, None]
+        reg = np.arange(16, dtype=np.int64)[None, :]
+        for ps in seg["passes"]:
+            kp = ps["kernel"]
+            out = np.zeros_like(psi)
+            written = np.zeros(psi.size, dtype=np.int64)
+            stages = kp["stages"]
+            for tile in range(1 << (n - b)):
+                base = 0
+                for r in kp["runs"]:
+                    src, ln, dst = r & 0xFF, (r >> 8) & 0xFF, r >> 16
+                    base |= ((tile >> src) & ((1 << ln) - 1)) << dst
+                lds = np.zeros(1 << b, dtype=np.complex128)
+                for si, S in enumerate(stages):
+                    if S["kind"] == 1:  # dense unitary on LDS
+                        k = S["k"]
+                        dim = 1 << k
+                        U = coefs[S["coef"]:S["coef"] + 2 * dim * dim]
+                        U = (U[0::2] + 1j * U[1::2]).reshape(dim, dim)
+                        cols = _xor_bits(S["col_off"], np.arange(1 << len(S["col_off"]), dtype=np.int64),
+                                         len(S["col_off"]))
+                        slots = np.array(S["row_off"], dtype=np.int64)[:, None] ^ cols[None, :]
+                        lds[slots] = U @ lds[slots]
+                        continue
+                    bt = _xor_bits(S["thr_off"], t, kp["n_thr"])
+                    sl = bt ^ _xor_bits(S["reg_bit"], reg, 4)
+                    if si == 0:
+                        g = base | _xor_bits(S["g_thr"], t, kp["n_thr"]) | _xor_bits(S["g_bit"], reg, 4)
+                        assert g.min() >= 0 and g.max() < psi.size
+                        a = psi[g].copy()
+                    else:
+                        a = lds[sl].copy()
+                    for op in S["ops"]:
+                        _apply_kop(a, op, coefs)
+                    if si + 1 == len(stages):
+                        g = base | _xor_bits(S["g_thr"], t, kp["n_thr"]) | _xor_bits(S["g_bit"], reg, 4)
+                        assert g.min() >= 0 and g.max() < psi.size
+                        out[g] = a
+                        np.add.at(written, g.ravel(), 1)
+                    else:
+                        lds[sl] = a
+            assert np.all(written == 1), "a pass must write every amplitude exactly once"
+            psi = out
+    return psi
+
+
+@pytest.mark.parametrize("relabel", [0, 1])
+@pytest.mark.parametrize("n,b,c,fam,fusion", [
+    (8, 6, 2, "dense", 1), (9, 6, 3, "layered", 1), (10, 7, 4, "ladder", 1), (11, 7, 5, "layered", 1),
+    (10, 6, 4, "dense", 0), (12, 10, 3, "layered", 2)])
+def test_kernel_emulation_of_plan_blobs_matches_oracle(n, b, c, fam, fusion, relabel):
+    """The blobs the kernel reads (maps, op records, coefficients) give the
+    oracle's state when run as the kernel runs them, with and without
+    relabelling passes, for list stages, dense 16x16 stages and matrix-core
+    stages."""
+    if fam == "dense":
+        nets = W.dense_random_circuit(n, 10, 90 + n, kinds=W.GATE_KINDS)
+    elif fam == "layered":
+        nets = W.layered_circuit(n, 6, 91 + n)
+    else:
+        nets = W.cp_ladder_circuit(n, 4, 92 + n)
+    kw = dict(tile_bits=b, low_bits=c, ckpt_interval=5, relabel=relabel, fusion=fusion)
+    if fusion == 2:
+        kw["fuse_width"] = 5
+    with plan_only(n, **kw) as sim:
+        sim.build(nets)
+        sim.update()
+        dump = sim.dump()
+    np.testing.assert_allclose(emulate_kernel(dump, n), oracle.simulate(n, nets), atol=1e-12)
