@@ -208,6 +208,18 @@ int qtask_norm(qtask_t h, double *out);
  * device; their dtypes may differ (a complex64 state against its complex128
  * reference). */
 int qtask_inner(qtask_t a, qtask_t b, double re_im[2]);
+/* qtask_inner without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The partial sums go to a fixed scratch array the
+ * library holds on each GPU until the process ends (4098 doubles, 32 KiB:
+ * enough for the reduction of any state up to 34 qubits, so no state size
+ * is refused; QTASK_E_UNSUPPORTED would name one that is).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (from several
+ * threads, or on several streams) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero: each call writes
+ * every partial it reads.  Same arguments, layout and errors as
+ * qtask_inner. */
+int qtask_inner_noalloc(qtask_t a, qtask_t b, double re_im[2]);
 /* Number of amplitude slots whose bytes differ between a and b (bitwise). */
 int qtask_compare_states(qtask_t a, qtask_t b, uint64_t *n_diff);
 /* Deterministic 64-bit hash of the state bytes. */

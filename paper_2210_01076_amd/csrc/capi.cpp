@@ -293,6 +293,36 @@ int qtask_inner(qtask_t a, qtask_t b, double re_im[2]) {
     });
 }
 
+int qtask_inner_noalloc(qtask_t a, qtask_t b, double re_im[2]) {
+    return guarded([&] {
+        Session *x = S(a), *y = S(b);
+        if (!x || !y || !re_im) return QTASK_E_ARG;
+        if (x->n != y->n) return QTASK_E_ARG;
+        if (x->plan_only || y->plan_only) return QTASK_E_UNSUPPORTED;
+        if (x->opts.device != y->opts.device) return QTASK_E_ARG;
+        if (!x->state_valid() || !y->state_valid() || x->circ.edited() || y->circ.edited()) return QTASK_E_STALE;
+        if (hipSetDevice(x->opts.device) != hipSuccess) return QTASK_E_DEVICE;
+        const uint64_t N = uint64_t(1) << x->n_int;
+        const uint32_t g = qtask::reduce_grid(N);
+        double *scr = nullptr;
+        size_t cap = 0;
+        if (qtask::noalloc_scratch(x->opts.device, &scr, &cap) != hipSuccess) return QTASK_E_DEVICE;
+        if (2 * size_t(g) + 2 > cap) {
+            x->last_error = "qtask_inner_noalloc: the reduction needs more partial sums than the fixed scratch holds";
+            return QTASK_E_UNSUPPORTED;
+        }
+        if (hipStreamSynchronize(y->stream) != hipSuccess) return QTASK_E_DEVICE;
+        double v[2] = {0, 0};
+        if (qtask::launch_inner(x->dtype, y->dtype, x->state(), y->state(), N, scr + 2, scr, x->stream) != hipSuccess ||
+            hipMemcpyAsync(v, scr, sizeof(v), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+            hipStreamSynchronize(x->stream) != hipSuccess)
+            return QTASK_E_DEVICE;
+        re_im[0] = v[0];
+        re_im[1] = v[1];
+        return QTASK_OK;
+    });
+}
+
 int qtask_compare_states(qtask_t a, qtask_t b, uint64_t *n_diff) {
     return guarded([&] {
         Session *x = S(a), *y = S(b);

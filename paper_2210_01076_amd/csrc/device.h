@@ -44,6 +44,11 @@ hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s);
 hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint32_t *blocks, uint32_t n_blocks,
                               int block_bits, hipStream_t s);
 
+// Device address (on `device`) and size of the library's fixed scratch
+// array for the allocation-free inner product; the address is looked up
+// once per device and cached.
+hipError_t noalloc_scratch(int device, double **ptr, size_t *doubles);
+
 // dst = src over n 32-byte words (plain streaming copy)
 hipError_t launch_copy(void *dst, const void *src, uint64_t n32, hipStream_t s);
 

@@ -20,6 +20,8 @@
 // the input and the plan.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.h"
 
 namespace qtask {
@@ -1111,6 +1113,40 @@ hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint3
     else
         hipLaunchKernelGGL(qk_copy_blocks<float>, dim3(g), dim3(256), 0, s, dst, src, blocks, n_blocks, block_bits);
     return hipGetLastError();
+}
+
+// --------------------------------------------- allocation-free scratch
+// Partial sums for the allocation-free inner product: a fixed device array
+// (one copy per GPU, held until the process ends), big enough for the
+// largest reduction grid (2 * reduce_grid(n) partials plus the two results).
+// Host code never passes the array's name to a kernel: that is a host-side
+// stand-in, not a device address.  The device address is taken once per
+// device with hipGetSymbolAddress, with that device current, and kept.
+constexpr size_t kNoallocScratchDoubles = 2 * 2048 + 2;
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {nullptr};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double **ptr, size_t *doubles) {
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    *doubles = kNoallocScratchDoubles;
+    return hipSuccess;
 }
 
 }  // namespace qtask

@@ -96,6 +96,7 @@ _SIGS = {
     "qtask_read_amplitudes": ([vp, u64, u64, vp], ctypes.c_int),
     "qtask_norm": ([vp, P(ctypes.c_double)], ctypes.c_int),
     "qtask_inner": ([vp, vp, P(ctypes.c_double)], ctypes.c_int),
+    "qtask_inner_noalloc": ([vp, vp, P(ctypes.c_double)], ctypes.c_int),
     "qtask_compare_states": ([vp, vp, P(u64)], ctypes.c_int),
     "qtask_state_hash": ([vp, P(u64)], ctypes.c_int),
     "qtask_state_device_ptr": ([vp, P(vp), P(u64)], ctypes.c_int),
@@ -246,6 +247,12 @@ def qtask_norm(h) -> float:
 def qtask_inner(a, b) -> complex:
     v = (ctypes.c_double * 2)()
     check(load().qtask_inner(a, b, v), "qtask_inner")
+    return complex(v[0], v[1])
+
+
+def qtask_inner_noalloc(a, b) -> complex:
+    v = (ctypes.c_double * 2)()
+    check(load().qtask_inner_noalloc(a, b, v), "qtask_inner_noalloc")
     return complex(v[0], v[1])
 
 
