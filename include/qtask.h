@@ -114,6 +114,12 @@ typedef struct qtask_opts {
                                sit in the contiguous low positions every tile holds (longer contiguous runs
                                per access at the same number of passes); each segment starts and ends in
                                the plain layout (qubit k at bit k), so checkpoints and queries see it */
+    int32_t ckpt_delta;     /* 1: sparse checkpoints (the paper's copy-on-write blocks, Section III-F): every
+                               segment boundary keeps a checkpoint (max_ckpts is ignored), holding only the blocks
+                               of 2^block_bits amplitudes that the segment before it can change (decided by the
+                               ops' kernel forms); a restore takes each block from the newest checkpoint holding
+                               it.  The affected-block replay (mode 3) is not used with them.  0 (default): whole
+                               copies */
 } qtask_opts;
 
 typedef struct qtask_s *qtask_t;
@@ -140,6 +146,8 @@ typedef struct qtask_stats {
     double pass_kernel_ms;     /* device time of the pass kernels alone */
     double plan_ms;            /* host planning time */
     double wall_ms;            /* wall time of the call */
+    uint64_t ckpt_bytes;       /* device bytes the stored checkpoints hold after the call */
+    uint64_t ckpt_full_bytes;  /* the same checkpoints as whole-state copies */
 } qtask_stats;
 
 /* ---------------------------------------------------------------- basics */

@@ -143,6 +143,7 @@ int qtask_create(int n_qubits, qtask_dtype dtype, const qtask_opts *user, qtask_
             return QTASK_E_UNSUPPORTED;  // matrix-core stages need tiles of >= 2^10 amplitudes
         if (o.ckpt_interval < 1 || o.max_ckpts < -1) return QTASK_E_ARG;
         if (o.relabel < -1 || o.relabel > 1) return QTASK_E_ARG;
+        if (o.ckpt_delta < 0 || o.ckpt_delta > 1) return QTASK_E_ARG;
         if (o.relabel == -1) o.relabel = std::max(n_qubits, QK_MIN_TILE_BITS) >= 26 ? 1 : 0;
         if (o.device < QTASK_DEVICE_NONE) return QTASK_E_ARG;
         if ((o.alloc == nullptr) != (o.free == nullptr)) return QTASK_E_ARG;

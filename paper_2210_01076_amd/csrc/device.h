@@ -40,9 +40,11 @@ hipError_t launch_hash(int dtype, const void *a, uint64_t n, unsigned long long 
                        unsigned long long *out, hipStream_t s);
 // state = |0...0>
 hipError_t launch_fill_basis(int dtype, void *state, uint64_t n, hipStream_t s);
-// dst[block] = src[block] for the listed blocks of 2^block_bits elements.
-hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint32_t *blocks, uint32_t n_blocks,
-                              int block_bits, hipStream_t s);
+// Block k of the list (2^block_bits elements) from source block src_idx[k]
+// to destination block dst_idx[k]; a null index list means k itself; a null
+// source fills the destination blocks with their part of |0...0>.
+hipError_t launch_block_copy(int dtype, void *dst, const void *src, const uint32_t *dst_idx, const uint32_t *src_idx,
+                             uint32_t n_blocks, int block_bits, hipStream_t s);
 
 // Device address (on `device`) and size of the library's fixed scratch
 // array for the allocation-free inner product; the address is looked up

@@ -43,8 +43,19 @@ enum KOpType : uint8_t {
     KOP_UX = 13,   // [[a, ib], [ic, d]] with a,b,c,d real (RX)  coef: a b c d (4)
     KOP_P1 = 14,   // diag(1, p) on bit a (Z, S, T, ...)         coef: p (2)
     KOP_P2 = 15,   // diag(1, 1, 1, p) on (a, b) (CZ, CP)        coef: p (2)
-    KOP_GPH = 16   // every amplitude times g (no qubits)       coef: g (2)
+    KOP_GPH = 16,  // every amplitude times g (no qubits)       coef: g (2)
+    KOP_PC = 17,   // phase p on the registers with bit a set, in the lanes where site b
+                   // (a lane or origin site code, below) is 1      coef: p (2)
+    KOP_PCL = 18,  // phase p for every register of the lanes where sites a and b are 1:
+                   // multiplied into the lane's pending factor    coef: p (2)
+    KOP_PHI = 19   // every register times the lane's pending factor (where one was
+                   // taken), which then resets to 1             coef: none
 };
+
+// Site codes of the phase ops: where a phase gate's qubit sits in the stage.
+#define KPC_LANE 16      // 16 + k: bit k of the thread index
+#define KPC_ORIGIN 64    // 64 + q: bit q of the tile's global origin (the qubit is not in the tile)
+#define KPC_NONE 255     // no qubit (the condition always holds)
 
 enum KStageKind : uint32_t {
     KSTAGE_LIST = 0,   // ops on registers (vector ALU)

@@ -228,6 +228,62 @@ __device__ __forceinline__ void op_gph(typename V2<R>::T (&a)[NR], const R *__re
     for (int i = 0; i < NR; ++i) cmul_in_place(a[i].x, a[i].y, gr, gi);
 }
 
+// Phase gates with a qubit off the stage's registers.  A site is a lane bit
+// (a per-lane condition, applied under the lane mask so that lanes where it
+// fails keep their bits untouched: a multiply by 1 + 0i could turn a -0 into
+// +0) or a bit of the tile origin (the same in every lane: a wave-uniform
+// branch skips the op where it fails).
+__device__ __forceinline__ bool origin_off(uint32_t s, uint64_t base) {
+    return s >= KPC_ORIGIN && s != KPC_NONE && !((base >> (s - KPC_ORIGIN)) & 1u);
+}
+__device__ __forceinline__ bool lane_on(uint32_t s, uint32_t t) {
+    return s < KPC_LANE || s >= KPC_ORIGIN || ((t >> (s - KPC_LANE)) & 1u);
+}
+
+// KOP_PC: p on the registers with bit A set, where site b holds.
+template <int A, typename R>
+__device__ __forceinline__ void op_pc(typename V2<R>::T (&a)[NR], const R *__restrict__ c, uint32_t site, uint32_t t,
+                                      uint64_t base) {
+    if (origin_off(site, base)) return;
+    if (lane_on(site, t)) {
+        const R pr = c[0], pi = c[1];
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if (i & (1 << A)) cmul_in_place(a[i].x, a[i].y, pr, pi);
+    }
+}
+
+// The lane's pending phase: phase gates whose qubits are all off the
+// registers scale every register of a lane alike, and they commute with
+// every register op of the stage, so their product is formed first (one
+// complex multiply each) and applied to the registers once, by KOP_PHI.
+template <typename R> struct Pending {
+    R r, i;
+    bool hit;
+};
+
+template <typename R>
+__device__ __forceinline__ void op_pcl(Pending<R> &ph, const R *__restrict__ c, uint32_t sa, uint32_t sb, uint32_t t,
+                                       uint64_t base) {
+    if (origin_off(sa, base) || origin_off(sb, base)) return;
+    if (lane_on(sa, t) && lane_on(sb, t)) {
+        cmul_in_place(ph.r, ph.i, c[0], c[1]);
+        ph.hit = true;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void op_phi(typename V2<R>::T (&a)[NR], Pending<R> &ph) {
+    if (ph.hit) {
+        const R pr = ph.r, pi = ph.i;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) cmul_in_place(a[i].x, a[i].y, pr, pi);
+    }
+    ph.r = R(1);
+    ph.i = R(0);
+    ph.hit = false;
+}
+
 #define SW1(F)                                   \
     switch (op.a) {                              \
     case 0: F<0>(a, c); break;              \
@@ -271,8 +327,17 @@ __device__ __forceinline__ void op_gph(typename V2<R>::T (&a)[NR], const R *__re
     default: break;                              \
     }
 
+#define SW1PC(F)                                           \
+    switch (op.a) {                                        \
+    case 0: F<0, R>(a, c, op.b, t, base); break;           \
+    case 1: F<1, R>(a, c, op.b, t, base); break;           \
+    case 2: F<2, R>(a, c, op.b, t, base); break;           \
+    default: F<3, R>(a, c, op.b, t, base); break;          \
+    }
+
 template <typename R>
-__device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR], const R *__restrict__ c) {
+__device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR], const R *__restrict__ c, uint32_t t,
+                                         uint64_t base, Pending<R> &ph) {
     // the rotations and the CX of layered circuits first: a wave-uniform
     // if-chain reaches them in one or two branches
     const uint32_t ty = op.type;
@@ -291,6 +356,9 @@ __device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR
         case KOP_P1: SW1(op_p1) break;
         case KOP_P2: SW2(op_p2) break;
         case KOP_GPH: op_gph<R>(a, c); break;
+        case KOP_PC: SW1PC(op_pc) break;
+        case KOP_PCL: op_pcl<R>(ph, c, op.a, op.b, t, base); break;
+        case KOP_PHI: op_phi<R>(a, ph); break;
         default: break;
         }
     }
@@ -353,11 +421,12 @@ __device__ __forceinline__ StageHead stage_head(const KStage *__restrict__ S) {
 // inside the plan blob, so the read past the last op stays in bounds).
 template <typename R>
 __device__ __forceinline__ void run_ops(const StageHead &h, const KOp *__restrict__ ops, const R *__restrict__ coefs,
-                                        typename V2<R>::T (&a)[NR], KOp &op) {
+                                        typename V2<R>::T (&a)[NR], KOp &op, uint32_t t, uint64_t base,
+                                        Pending<R> &ph) {
     const uint32_t oe = h.op_begin + h.op_count;
     for (uint32_t oi = h.op_begin; oi < oe; ++oi) {
         const KOp nx = ops[oi + 1];
-        apply_op<R>(op, a, coefs + op.coef);
+        apply_op<R>(op, a, coefs + op.coef, t, base, ph);
         op = nx;
     }
 }
@@ -591,6 +660,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     // scatters back to LDS.  (One call site keeps the amplitude registers
     // in place across the whole pass.)
     C a[NR];
+    Pending<R> ph{R(1), R(0), false};
     KOp op = ops[S0->op_begin];
     for (uint32_t si = 0; si < ns; ++si) {
         const KStage *__restrict__ S = S0 + si;
@@ -634,7 +704,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
                 a[i].y = y.y;
             }
         }
-        run_ops<R>(h, ops, coefs, a, op);
+        run_ops<R>(h, ops, coefs, a, op, t, base, ph);
         if (si + 1 == ns) break;
         // complex128: recompute the slots instead of keeping them live across
         // the op loop (16 fewer registers; see the kernel's occupancy hint)
@@ -928,16 +998,31 @@ __global__ void qk_fill_basis(void *state_, uint64_t n) {
     }
 }
 
+// Whole blocks of 2^block_bits amplitudes: block k of the list goes from
+// source block src_idx[k] to destination block dst_idx[k] (a missing index
+// list means the block number k itself).  Without a source the destination
+// blocks get the matching part of |0...0>.  Used to capture and restore
+// sparse checkpoints (only the blocks a segment can change).
 template <typename R>
-__global__ void qk_copy_blocks(void *dst_, const void *src_, const uint32_t *blocks, uint32_t n_blocks,
-                               int block_bits) {
+__global__ void qk_block_copy(void *dst_, const void *src_, const uint32_t *dst_idx, const uint32_t *src_idx,
+                              uint32_t n_blocks, int block_bits) {
     using C = typename V2<R>::T;
     C *dst = static_cast<C *>(dst_);
     const C *src = static_cast<const C *>(src_);
     const uint64_t bsz = uint64_t(1) << block_bits;
     for (uint32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
-        const uint64_t off = uint64_t(blocks[bi]) << block_bits;
-        for (uint64_t i = threadIdx.x; i < bsz; i += blockDim.x) dst[off + i] = src[off + i];
+        const uint64_t d = uint64_t(dst_idx ? dst_idx[bi] : bi) << block_bits;
+        if (src) {
+            const uint64_t so = uint64_t(src_idx ? src_idx[bi] : bi) << block_bits;
+            for (uint64_t i = threadIdx.x; i < bsz; i += blockDim.x) dst[d + i] = src[so + i];
+        } else {
+            for (uint64_t i = threadIdx.x; i < bsz; i += blockDim.x) {
+                C z;
+                z.x = d + i == 0 ? R(1) : R(0);
+                z.y = R(0);
+                dst[d + i] = z;
+            }
+        }
     }
 }
 
@@ -1104,14 +1189,17 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t n32, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_copy_blocks(int dtype, void *dst, const void *src, const uint32_t *blocks, uint32_t n_blocks,
-                              int block_bits, hipStream_t s) {
+hipError_t launch_block_copy(int dtype, void *dst, const void *src, const uint32_t *dst_idx, const uint32_t *src_idx,
+                             uint32_t n_blocks, int block_bits, hipStream_t s) {
+    (void)hipGetLastError();
     if (n_blocks == 0) return hipSuccess;
     const uint32_t g = n_blocks < 65535 ? n_blocks : 65535;
     if (dtype == 0)
-        hipLaunchKernelGGL(qk_copy_blocks<double>, dim3(g), dim3(256), 0, s, dst, src, blocks, n_blocks, block_bits);
+        hipLaunchKernelGGL(qk_block_copy<double>, dim3(g), dim3(256), 0, s, dst, src, dst_idx, src_idx, n_blocks,
+                           block_bits);
     else
-        hipLaunchKernelGGL(qk_copy_blocks<float>, dim3(g), dim3(256), 0, s, dst, src, blocks, n_blocks, block_bits);
+        hipLaunchKernelGGL(qk_block_copy<float>, dim3(g), dim3(256), 0, s, dst, src, dst_idx, src_idx, n_blocks,
+                           block_bits);
     return hipGetLastError();
 }
 

@@ -142,13 +142,17 @@ LGate merge_1q(const LGate &later, const LGate &earlier) {
 // A diagonal one-qubit op diag(d0, d1) runs as diag(1, d1/d0), which
 // multiplies half the amplitudes instead of all of them; the factors d0 of a
 // segment are collected, in plan order, into one scalar that the segment's
-// last stage applies to every amplitude.  A scalar factor commutes with every
-// gate, so the segment's result is unchanged up to rounding.  Plans whose
-// last stage is a fused dense unitary keep their diagonal ops as they are.
+// last list stage applies to every amplitude.  A scalar factor commutes with
+// every gate, so the segment's result is unchanged up to rounding.
 void factor_phases(std::vector<PPass> &passes) {
-    if (passes.empty() || passes.back().stages.empty()) return;
-    PStage &last = passes.back().stages.back();
-    if (!last.U.empty() || last.mfma) return;
+    // the scalar commutes with every op, so any list stage can hold it: the
+    // last one of the segment
+    PStage *lastp = nullptr;
+    for (auto &ps : passes)
+        for (auto &st : ps.stages)
+            if (st.U.empty() && !st.mfma) lastp = &st;
+    if (!lastp) return;
+    PStage &last = *lastp;
     cd g(1, 0);
     bool any = false;
     for (auto &ps : passes)
@@ -212,14 +216,25 @@ struct Packer {
         int8_t tbit[64];
         for (int q = 0; q < 64; ++q) tbit[q] = -1;
         for (size_t p = 0; p < ps.qlist.size(); ++p) tbit[ps.qlist[p]] = int8_t(p);
-        std::vector<uint32_t> tmask(ops.size());
+        // need: the tile bits an op must have on registers; dep: the tile
+        // bits it is ordered on (a free phase needs none, and a qubit it has
+        // outside the tile is touched by no other op of the pass but free
+        // phases, which commute with it)
+        Masks mask64;
+        mask64.need.resize(ops.size());
+        mask64.dep.resize(ops.size());
         for (size_t i = 0; i < ops.size(); ++i) {
-            uint32_t m = 0;
+            uint64_t m = 0;
+            const bool fp = free_phase(*ops[i]);
             for (int j = 0; j < ops[i]->nq; ++j) {
-                if (tbit[ops[i]->q[j]] < 0) throw std::logic_error("qubit not in pass");
-                m |= 1u << tbit[ops[i]->q[j]];
+                if (tbit[ops[i]->q[j]] < 0) {
+                    if (!fp) throw std::logic_error("qubit not in pass");
+                    continue;
+                }
+                m |= uint64_t(1) << tbit[ops[i]->q[j]];
             }
-            tmask[i] = m;
+            mask64.dep[i] = m;
+            mask64.need[i] = fp ? 0 : m;
         }
         std::vector<size_t> rem(ops.size());
         for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
@@ -229,7 +244,6 @@ struct Packer {
         // packed from gates above them when there are any; the others wait.
         const uint32_t low_mask = (1u << std::min(coalesce_bits(), pp.b - QK_G)) - 1;
         bool first = true;
-        const std::vector<uint64_t> mask64(tmask.begin(), tmask.end());
         auto fill = [&](uint64_t S) {
             for (int p = pp.b - 1; p >= 0 && popc(S) < W; --p) S |= uint64_t(1) << p;
             return S;
@@ -253,15 +267,16 @@ struct Packer {
             for (int p = 0; p < pp.b; ++p)
                 if (!((S >> p) & 1)) others.push_back(p);
             st.tpos = lane_order(others, pp.swz);
-            // ops, merging consecutive one-qubit gates on the same qubit
+            // ops, merging consecutive one-qubit gates on the same register qubit
             std::vector<int> last(pp.b, -1);
             st.ops.reserve(take.size());
+            bool off_register = false;  // some free phase has a qubit off the registers
+            auto on_reg = [&](int q) { return tbit[q] >= 0 && ((S >> tbit[q]) & 1); };
             for (size_t idx : take) {
                 const LGate &g = *ops[idx];
-                if (mergeable(g)) {
-                    const int tb = tbit[g.q[0]];
-                    const int li = last[tb];
-                    if (li >= 0 && mergeable(st.ops[li])) {
+                if (mergeable(g) && on_reg(g.q[0])) {
+                    const int li = last[tbit[g.q[0]]];
+                    if (li >= 0 && mergeable(st.ops[li]) && on_reg(st.ops[li].q[0])) {
                         LGate mg = merge_1q(g, st.ops[li]);
                         if (op_cost(mg) <= op_cost(g) + op_cost(st.ops[li])) {
                             st.ops[li] = mg;
@@ -270,7 +285,10 @@ struct Packer {
                     }
                 }
                 st.ops.push_back(g);
-                for (int j = 0; j < g.nq; ++j) last[tbit[g.q[j]]] = int(st.ops.size()) - 1;
+                for (int j = 0; j < g.nq; ++j) {
+                    if (tbit[g.q[j]] >= 0) last[tbit[g.q[j]]] = int(st.ops.size()) - 1;
+                    off_register = off_register || !on_reg(g.q[j]);
+                }
             }
             double fl = 0;
             for (const auto &g : st.ops) fl += g.flops_per_amp();
@@ -284,7 +302,7 @@ struct Packer {
                 // unitary on smaller tiles runs on registers instead
                 st.mfma = pp.b >= 10 && pp.b - W >= 4;
                 if (!st.mfma && W != QK_G) throw std::invalid_argument("dense fusion width needs tile_bits >= 10");
-            } else if (pp.fusion == QTASK_FUSE_AUTO && fl > dense_fl) {
+            } else if (pp.fusion == QTASK_FUSE_AUTO && fl > dense_fl && !off_register) {
                 make_dense = true;  // dense 16x16 on registers is cheaper than the list
             }
             if (make_dense) {
@@ -362,32 +380,38 @@ struct Packer {
 
     // Packing a pass (a qubit set of at most b qubits) and packing a stage
     // (a set of at most QK_G tile bits) are the same problem over bit masks:
-    // pick a set, then run every pending op whose bits lie in it and that no
-    // earlier deferred op blocks.  `forbid` bits may not join the set (the
-    // first stage keeps the lowest tile bits on the lanes).
+    // pick a set, then run every pending op whose `need` bits lie in it and
+    // that no earlier deferred op blocks.  An op's `dep` bits are the ones it
+    // shares an order with: a deferred op blocks every later op that shares
+    // a dep bit with it.  need == dep except for the free phases (diagonal
+    // ops that run on any set: need is empty).  `forbid` bits may not join
+    // the set (the first stage keeps the lowest tile bits on the lanes).
+    struct Masks {
+        std::vector<uint64_t> need, dep;
+    };
 
     // Ops of `rem` (in order) that a set Q can apply.
-    static size_t count_applicable(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t Q,
-                                   uint64_t forbid, size_t limit) {
+    static size_t count_applicable(const Masks &mk, const std::vector<size_t> &rem, uint64_t Q, uint64_t forbid,
+                                   size_t limit) {
         uint64_t blocked = forbid;
         size_t cnt = 0;
         for (size_t i = 0; i < rem.size() && i < limit; ++i) {
-            const uint64_t m = mask[rem[i]];
-            if ((m & blocked) || (m & ~Q)) blocked |= m;
+            const uint64_t d = mk.dep[rem[i]];
+            if ((d & blocked) || (mk.need[rem[i]] & ~Q)) blocked |= d;
             else ++cnt;
         }
         return cnt;
     }
 
     // First fit in program order: each pending op extends the set while it fits.
-    static uint64_t first_fit_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
-                                  int cap, uint64_t forbid) {
+    static uint64_t first_fit_set(const Masks &mk, const std::vector<size_t> &rem, uint64_t start, int cap,
+                                  uint64_t forbid) {
         uint64_t Q = start, blocked = forbid;
         for (size_t idx : rem) {
-            const uint64_t m = mask[idx];
-            if (m & blocked) { blocked |= m; continue; }
+            const uint64_t d = mk.dep[idx], m = mk.need[idx];
+            if (d & blocked) { blocked |= d; continue; }
             if (popc(Q | m) <= cap) Q |= m;
-            else blocked |= m;
+            else blocked |= d;
         }
         return Q;
     }
@@ -395,8 +419,8 @@ struct Packer {
     // Gain-driven choice: grow the set by the new bits of one of the first
     // pending ops, picking the addition that makes the most ops of the
     // look-ahead window applicable per added bit.
-    static uint64_t gain_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
-                             int cap, uint64_t forbid) {
+    static uint64_t gain_set(const Masks &mk, const std::vector<size_t> &rem, uint64_t start, int cap,
+                             uint64_t forbid) {
         constexpr size_t kWindow = 128, kCands = 8;
         uint64_t Q = start;
         std::vector<uint64_t> cands;
@@ -404,19 +428,19 @@ struct Packer {
             cands.clear();
             uint64_t blocked = forbid;
             for (size_t i = 0; i < rem.size() && cands.size() < kCands; ++i) {
-                const uint64_t m = mask[rem[i]];
+                const uint64_t m = mk.need[rem[i]], d = mk.dep[rem[i]];
                 const uint64_t add = m & ~Q;
                 if (!add) continue;
-                if (!(m & blocked) && popc(Q | add) <= cap &&
+                if (!(d & blocked) && popc(Q | add) <= cap &&
                     std::find(cands.begin(), cands.end(), add) == cands.end())
                     cands.push_back(add);
-                blocked |= m;
+                blocked |= d;
             }
             if (cands.empty()) break;
             uint64_t best = cands.front();
             double best_v = -1;
             for (uint64_t add : cands) {
-                const double v = double(count_applicable(mask, rem, Q | add, forbid, kWindow)) / popc(add);
+                const double v = double(count_applicable(mk, rem, Q | add, forbid, kWindow)) / popc(add);
                 if (v > best_v) { best_v = v; best = add; }
             }
             Q |= best;
@@ -426,26 +450,35 @@ struct Packer {
 
     // The better of the two sets (more ops applicable), after `fill` tops it up.
     template <typename Fill>
-    static uint64_t choose_set(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t start,
-                               int cap, uint64_t forbid, Fill fill) {
-        const uint64_t Qf = fill(first_fit_set(mask, rem, start, cap, forbid));
-        const uint64_t Qg = fill(gain_set(mask, rem, start, cap, forbid));
-        const size_t nf = count_applicable(mask, rem, Qf, forbid, rem.size());
-        const size_t ng = count_applicable(mask, rem, Qg, forbid, rem.size());
+    static uint64_t choose_set(const Masks &mk, const std::vector<size_t> &rem, uint64_t start, int cap,
+                               uint64_t forbid, Fill fill) {
+        const uint64_t Qf = fill(first_fit_set(mk, rem, start, cap, forbid));
+        const uint64_t Qg = fill(gain_set(mk, rem, start, cap, forbid));
+        const size_t nf = count_applicable(mk, rem, Qf, forbid, rem.size());
+        const size_t ng = count_applicable(mk, rem, Qg, forbid, rem.size());
         return ng > nf ? Qg : Qf;
     }
 
     // Split rem into the ops the set runs (take) and the rest (left).
-    static void split_ops(const std::vector<uint64_t> &mask, const std::vector<size_t> &rem, uint64_t Q,
-                          uint64_t forbid, std::vector<size_t> &take, std::vector<size_t> &left) {
+    static void split_ops(const Masks &mk, const std::vector<size_t> &rem, uint64_t Q, uint64_t forbid,
+                          std::vector<size_t> &take, std::vector<size_t> &left) {
         take.clear();
         left.clear();
         uint64_t blocked = forbid;
         for (size_t idx : rem) {
-            const uint64_t m = mask[idx];
-            if ((m & blocked) || (m & ~Q)) { blocked |= m; left.push_back(idx); }
+            const uint64_t d = mk.dep[idx];
+            if ((d & blocked) || (mk.need[idx] & ~Q)) { blocked |= d; left.push_back(idx); }
             else take.push_back(idx);
         }
+    }
+
+    // A free phase: a diagonal op (phase or diagonal one-qubit matrix) that
+    // runs wherever it falls, whichever of its qubits the tile or the stage
+    // holds -- the kernel then conditions it on lane bits or on the tile
+    // origin.  Not with dense fusion, whose stages fold their ops into one
+    // unitary over the stage's own bits.
+    bool free_phase(const LGate &g) const {
+        return pp.fusion != QTASK_FUSE_DENSE && (g.kop == KOP_P1 || g.kop == KOP_P2 || g.kop == KOP_D1);
     }
 
     // One pass: its physical tile positions, the ops it runs (already on
@@ -471,8 +504,13 @@ struct Packer {
         // every pass can take at least the first pending gate
         const int c = std::max(0, std::min(pp.c, pp.b - 3));
         const uint64_t low = (uint64_t(1) << c) - 1;
-        std::vector<uint64_t> mask(ops.size());
-        for (size_t i = 0; i < ops.size(); ++i) mask[i] = ops[i].mask();
+        Masks mask;
+        mask.need.resize(ops.size());
+        mask.dep.resize(ops.size());
+        for (size_t i = 0; i < ops.size(); ++i) {
+            mask.dep[i] = ops[i].mask();
+            mask.need[i] = free_phase(ops[i]) ? 0 : mask.dep[i];
+        }
         std::vector<size_t> rem(ops.size());
         for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
         std::vector<PPass> passes;
@@ -512,8 +550,13 @@ struct Packer {
         const int c = std::max(0, std::min(pp.c, pp.b - 3));
         std::vector<int> pos(static_cast<size_t>(n)), occ(static_cast<size_t>(n));  // circuit qubit -> position, position -> qubit
         for (int q = 0; q < n; ++q) pos[size_t(q)] = occ[size_t(q)] = q;
-        std::vector<uint64_t> mask(ops.size());
-        for (size_t i = 0; i < ops.size(); ++i) mask[i] = ops[i].mask();
+        Masks mask;
+        mask.need.resize(ops.size());
+        mask.dep.resize(ops.size());
+        for (size_t i = 0; i < ops.size(); ++i) {
+            mask.dep[i] = ops[i].mask();
+            mask.need[i] = free_phase(ops[i]) ? 0 : mask.dep[i];
+        }
         std::vector<size_t> rem(ops.size());
         for (size_t i = 0; i < rem.size(); ++i) rem[i] = i;
         std::vector<PPass> passes;
@@ -602,6 +645,7 @@ struct Packer {
                 size_t found = 0;
                 for (size_t k = 0; k < rem.size() && found < tq.size(); ++k) {
                     const LGate &g = ops[rem[k]];
+                    if (!mask.need[rem[k]]) continue;  // a free phase needs no tile position
                     for (int j = 0; j < g.nq; ++j)
                         if (next[size_t(g.q[j])] == kNever && ((Q >> g.q[j]) & 1)) {
                             next[size_t(g.q[j])] = k;
@@ -656,7 +700,10 @@ void pack_blob(SegmentPlan &sp) {
             ++n_stage;
             if (st.mfma) n_coef += st.U.size() * 2;
             else if (!st.U.empty()) { n_op += 1; n_coef += st.U.size() * 2; }
-            else for (const auto &g : st.ops) { ++n_op; n_coef += g.coef.size(); }
+            else {
+                for (const auto &g : st.ops) { ++n_op; n_coef += g.coef.size(); }
+                ++n_op;  // room for the stage's KOP_PHI
+            }
         }
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t bytes_pass = align(sp.passes.size() * sizeof(KPass));
@@ -744,15 +791,69 @@ void pack_blob(SegmentPlan &sp) {
                 o.coef = uint32_t(ci);
                 for (const cd &z : st.U) { kc[ci++] = R(z.real()); kc[ci++] = R(z.imag()); }
             } else {
+                // where a qubit sits in the stage: register bit j (j), lane
+                // bit k (KPC_LANE + k), or off the tile (KPC_ORIGIN + its
+                // position: a bit of the tile origin)
+                auto code_of = [&](int q) -> uint8_t {
+                    int tb = -1;
+                    for (size_t p = 0; p < ps.qlist.size(); ++p)
+                        if (ps.qlist[p] == q) tb = int(p);
+                    if (tb < 0) return uint8_t(KPC_ORIGIN + q);
+                    for (int j = 0; j < G; ++j)
+                        if (st.tbits[j] == tb) return uint8_t(j);
+                    for (int k = 0; k < n_thr; ++k)
+                        if (st.tpos[k] == tb) return uint8_t(KPC_LANE + k);
+                    throw std::logic_error("op qubit outside its pass");
+                };
+                // Phases with no qubit on the registers (and the global
+                // phase) scale whole lanes: they commute with every op of the
+                // stage, so they go last, into the lane's pending factor,
+                // which one KOP_PHI then applies.
+                std::vector<const LGate *> lane_phases;
                 for (const LGate &g : st.ops) {
+                    if (lane_phase(ps, st, g)) {
+                        if (g.kop != KOP_GPH && g.kop != KOP_P1 && g.kop != KOP_P2)
+                            throw std::logic_error("off-register op is no phase");
+                        lane_phases.push_back(&g);
+                        continue;
+                    }
+                    bool regs = true;
+                    for (int j = 0; j < g.nq; ++j) regs = regs && code_of(g.q[j]) < G;
                     KOp &o = ko[oi++];
+                    o.coef = uint32_t(ci);
+                    if (!regs) {
+                        // a free phase with one qubit on the registers and
+                        // the other on a lane or off the tile
+                        if (g.kop != KOP_P2) throw std::logic_error("off-register op is no phase");
+                        const uint8_t c0 = code_of(g.q[0]), c1 = code_of(g.q[1]);
+                        o.type = KOP_PC;
+                        o.a = c0 < G ? c0 : c1;
+                        o.b = c0 < G ? c1 : c0;
+                        o.c = 0;
+                        for (double v : g.coef) kc[ci++] = R(v);
+                        continue;
+                    }
                     o.type = g.kop;
                     o.a = g.nq > 0 ? uint8_t(reg_of(g.q[0])) : 0;
                     o.b = g.nq > 1 ? uint8_t(reg_of(g.q[1])) : 0;
                     o.c = g.nq > 2 ? uint8_t(reg_of(g.q[2])) : 0;
                     if (g.kop == KOP_CCX && o.a > o.b) std::swap(o.a, o.b);
-                    o.coef = uint32_t(ci);
                     for (double v : g.coef) kc[ci++] = R(v);
+                }
+                for (const LGate *g : lane_phases) {
+                    KOp &o = ko[oi++];
+                    o.type = KOP_PCL;
+                    o.a = g->nq > 0 ? code_of(g->q[0]) : uint8_t(KPC_NONE);
+                    o.b = g->nq > 1 ? code_of(g->q[1]) : uint8_t(KPC_NONE);
+                    o.c = 0;
+                    o.coef = uint32_t(ci);
+                    for (double v : g->coef) kc[ci++] = R(v);
+                }
+                if (!lane_phases.empty()) {
+                    KOp &o = ko[oi++];
+                    o.type = KOP_PHI;
+                    o.a = o.b = o.c = 0;
+                    o.coef = uint32_t(ci);
                 }
             }
             S.op_count = uint32_t(oi) - S.op_begin;
@@ -762,6 +863,15 @@ void pack_blob(SegmentPlan &sp) {
 
 
 }  // namespace
+
+bool lane_phase(const PPass &ps, const PStage &st, const LGate &g) {
+    if (g.kop == KOP_GPH) return true;
+    if (g.nq == 0 || !st.U.empty() || st.mfma) return false;
+    for (int j = 0; j < g.nq; ++j)
+        for (int tb : st.tbits)
+            if (ps.qlist[size_t(tb)] == g.q[j]) return false;
+    return true;
+}
 
 uint32_t lds_phys(uint32_t l, int swz) {
     uint32_t x = l;
@@ -902,7 +1012,10 @@ std::string validate_plan(const SegmentPlan &sp) {
             uint64_t sq = 0;
             for (int p : st.tbits) sq |= uint64_t(1) << ps.qlist[p];
             for (const auto &g : st.ops)
-                if ((g.mask() & ~sq) != 0) { err << "pass " << pi << " stage " << s << ": op outside stage"; return err.str(); }
+                if ((g.mask() & ~sq) != 0 && g.kop != KOP_P1 && g.kop != KOP_P2) {
+                    err << "pass " << pi << " stage " << s << ": op outside stage";
+                    return err.str();
+                }
         }
     }
     if (gates != sp.n_gates) { err << "gate count " << gates << " != " << sp.n_gates; return err.str(); }

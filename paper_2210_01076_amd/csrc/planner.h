@@ -50,6 +50,12 @@ struct PPass {
     int out_pos(int p) const { return out.empty() ? qlist[size_t(p)] : out[size_t(p)]; }
 };
 
+// A phase the kernel folds into each lane's pending factor: the global phase,
+// or a phase gate none of whose qubits is on the stage's registers.  Such ops
+// run after the stage's other ops, multiplied together first, and the
+// product then scales the lane's registers once.
+bool lane_phase(const PPass &ps, const PStage &st, const LGate &g);
+
 struct SegmentPlan {
     PlanParams pp;
     std::vector<PPass> passes;

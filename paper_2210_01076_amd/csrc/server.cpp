@@ -547,11 +547,12 @@ void qtask_server_s::run() {
                 fail(sid, rc, rc != QTASK_E_DEVICE);
                 continue;
             }
-            // the batched kernel has no matrix-core stages: such plans run
-            // on the session's own stream
-            bool mfma = false;
-            for (const auto &l : ss.s->launches) mfma = mfma || l.args.has_mfma;
-            ss.batched = ss.small && !mfma;
+            // the batched kernel runs pass launches without matrix-core
+            // stages: other plans (and sparse-checkpoint copies) run on the
+            // session's own stream
+            bool own = ss.s->opts.ckpt_delta != 0;
+            for (const auto &l : ss.s->launches) own = own || l.args.has_mfma || l.kind != 0;
+            ss.batched = ss.small && !own;
             if (ss.batched) {
                 // plan uploads went to the session's stream
                 if (hipStreamSynchronize(ss.s->stream) != hipSuccess) {

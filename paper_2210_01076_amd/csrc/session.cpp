@@ -93,13 +93,18 @@ int Session::init_device() {
     return QTASK_OK;
 }
 
+// With at most max_ckpts checkpoints, every stride-th boundary keeps one.
+// The stride only grows (when the boundaries outgrow it), so a circuit that
+// gains or loses a segment keeps its stored boundaries and their checkpoints.
 bool Session::stores_ckpt(size_t j, size_t S) const {
     if (j == 0 || j >= S) return false;
-    if (opts.max_ckpts < 0) return true;
+    if (opts.max_ckpts < 0 || opts.ckpt_delta) return true;
     if (opts.max_ckpts == 0) return false;
     const size_t nb = S - 1;
-    const size_t stride = (nb + size_t(opts.max_ckpts) - 1) / size_t(opts.max_ckpts);
-    return j % std::max<size_t>(stride, 1) == 0;
+    size_t stride = std::max<size_t>(ckpt_stride_, 1);
+    while (nb / stride > size_t(opts.max_ckpts)) ++stride;
+    ckpt_stride_ = stride;
+    return j % stride == 0;
 }
 
 uint64_t Session::planned_bytes() const {
@@ -112,7 +117,8 @@ uint64_t Session::planned_bytes() const {
 
 uint64_t Session::device_bytes() const {
     uint64_t b = state_.bytes;
-    for (const auto &kv : ckpts_) b += kv.second.buf.bytes;
+    for (const auto &kv : ckpts_) b += kv.second.buf.bytes + kv.second.d_blocks.bytes;
+    b += restore_cap_ * sizeof(uint32_t);
     for (const auto &kv : plan_cache_) b += kv.second.dev_bytes;
     b += (scalars_cap_ + partials_cap_) * sizeof(double) + u64_cap_ * sizeof(unsigned long long) +
          tiles_cap_ * sizeof(uint32_t) + mask_cap_ * sizeof(uint64_t);
@@ -200,6 +206,59 @@ size_t Session::slot_of(uint64_t anchor) {
     const size_t sl = next_slot_++;
     slots_.emplace(anchor, sl);
     return sl;
+}
+
+// Blocks of 2^block_bits amplitudes that a segment's plan can change, by
+// the kernel form of its ops (empty: every block).  A fused dense stage, a
+// store permutation, a segment scalar and a renormalised complex64 segment
+// change every block; otherwise each op changes the blocks it rewrites.
+const std::vector<uint32_t> &Session::written_blocks(const SegmentPlan &sp) {
+    auto it = wsets_.find(sp.hash);
+    if (it != wsets_.end()) return it->second;
+    std::vector<uint32_t> out;
+    const int beta = std::min(opts.block_bits, n_int);
+    const uint64_t nblocks = uint64_t(1) << (n_int - beta);
+    bool all = dtype == QTASK_C64 && opts.renorm != 0;
+    BlockSet w(nblocks);
+    for (const auto &p : sp.passes) {
+        if (all) break;
+        if (p.relabels()) { all = true; break; }
+        for (const auto &st : p.stages) {
+            if (!st.U.empty() || st.mfma) { all = true; break; }
+            for (const auto &g : st.ops) {
+                if (rewrites_every_block(g, beta)) {
+                    all = true;
+                    break;
+                }
+                for_rewritten_blocks(g, beta, nblocks, [&](uint64_t k) { w.set(k); });
+            }
+            if (all) break;
+        }
+    }
+    if (!all && w.count() < nblocks) out = w.list();
+    uint64_t key = 0;
+    if (!out.empty()) {
+        key = 0x44454c5441ull;
+        for (uint32_t b : out) key = hash_mix(key, b);
+    }
+    wkeys_[sp.hash] = key;
+    return wsets_.emplace(sp.hash, std::move(out)).first->second;
+}
+
+// The checkpoint layout of boundary j (the state before segment j).
+Session::CkptLayout Session::layout_of(size_t j) const {
+    CkptLayout L;
+    L.bytes = state_bytes();
+    if (!opts.ckpt_delta) return L;
+    const SegmentPlan &sp = *plans_[j - 1];
+    auto it = wsets_.find(sp.hash);
+    if (it == wsets_.end() || it->second.empty()) return L;
+    const int beta = std::min(opts.block_bits, n_int);
+    L.full = false;
+    L.blocks = &it->second;
+    L.wkey = wkeys_.at(sp.hash);
+    L.bytes = uint64_t(it->second.size()) * (uint64_t(1) << beta) * elem;
+    return L;
 }
 
 int Session::ensure_state() {
@@ -355,18 +414,23 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
         // bound is saturated at once (relabelling moves many ops to other
         // positions, and each would otherwise walk all blocks)
         bool sat = false;
-        auto add = [&](const LGate &g) {
-            if (!(g.kop == KOP_P1 || g.kop == KOP_P2 || g.kop == KOP_CX || g.kop == KOP_CCX || g.kop == KOP_SWAP)) {
-                sat = true;
-                return;
-            }
-            for_rewritten_blocks(g, beta, nblocks, [&](uint64_t k) { lb.set(k); });
-        };
-        while (!sat && (i < a.size() || j < b.size())) {
-            if (j == b.size() || (i < a.size() && a[i].first < b[j].first)) add(*a[i++].second);
-            else if (i == a.size() || b[j].first < a[i].first) add(*b[j++].second);
+        std::vector<const LGate *> diff;
+        while (i < a.size() || j < b.size()) {
+            if (j == b.size() || (i < a.size() && a[i].first < b[j].first)) diff.push_back(a[i++].second);
+            else if (i == a.size() || b[j].first < a[i].first) diff.push_back(b[j++].second);
             else { ++i; ++j; }
         }
+        for (const LGate *g : diff) sat = sat || rewrites_every_block(*g, beta);
+        if (sat) return QTASK_E_UNSUPPORTED;
+        // the bound walks every block per op: give up on the restriction
+        // when that would cost more than planning a replay saves
+        size_t actions = diff.size();
+        for (size_t s = s_edit; s < nseg; ++s)
+            for (const auto &p : plans_[s]->passes)
+                for (const auto &stg : p.stages) actions += stg.U.empty() ? stg.ops.size() : 1;
+        if (actions * nblocks > (uint64_t(1) << 28)) return QTASK_E_UNSUPPORTED;
+        for (size_t k = 0; k < diff.size() && !sat; ++k)
+            for_rewritten_blocks(*diff[k], beta, nblocks, [&](uint64_t blk) { lb.set(blk); });
         sat = sat || lb.all();
         for (size_t s = s_edit; s < nseg && !sat; ++s)
             for (const auto &p : plans_[s]->passes) {
@@ -401,12 +465,32 @@ int Session::try_closed(size_t s0, size_t s_edit, BlockSet &S) {
                     for (uint64_t j = 0; j < nblocks; ++j) mix(j, id);
                     continue;
                 }
-                for (const auto &g : stg.ops) {
+                auto op_id = [&](const LGate &g) {
                     uint64_t id = hash_mix(1469598103934665603ull, g.kop);
                     for (int q = 0; q < g.nq; ++q) id = hash_mix(id, uint64_t(g.q[q] + 1));
                     for (const cd &z : g.m) id = hash_mix(hash_mix(id, double_bits(z.real())), double_bits(z.imag()));
-                    for_rewritten_blocks(g, beta, nblocks, [&](uint64_t j) { mix(j, id); });
-                }
+                    return id;
+                };
+                for (const auto &g : stg.ops)
+                    if (!lane_phase(p, stg, g)) {
+                        const uint64_t id = op_id(g);
+                        for_rewritten_blocks(g, beta, nblocks, [&](uint64_t j) { mix(j, id); });
+                    }
+                // the stage's lane phases come last, multiplied into one
+                // factor per lane before it scales the registers: a block's
+                // bits depend on which of them share a stage
+                std::vector<uint64_t> hit;
+                for (const auto &g : stg.ops)
+                    if (lane_phase(p, stg, g)) {
+                        const uint64_t id = hash_mix(op_id(g), 0x50454e44ull);
+                        for_rewritten_blocks(g, beta, nblocks, [&](uint64_t j) {
+                            mix(j, id);
+                            hit.push_back(j);
+                        });
+                    }
+                std::sort(hit.begin(), hit.end());
+                hit.erase(std::unique(hit.begin(), hit.end()), hit.end());
+                for (uint64_t j : hit) mix(j, 0x504849ull);
             }
             // a store permutation moves every amplitude of the tile's
             // positions: it counts as rewriting every block
@@ -535,13 +619,19 @@ int Session::plan_update(bool force_full) {
         s_edit = S ? S - 1 : 0;
         for (size_t s = 0; s < S; ++s)
             if (segs_[s].hi > L) { s_edit = s; break; }
-        for (size_t j = s_edit; j >= 1; --j) {
+        auto usable = [&](size_t j) {
             auto it = ckpts_.find(segs_[j - 1].anchor);
-            if (stores_ckpt(j, S) && it != ckpts_.end() && it->second.valid && segs_[j - 1].hi <= L &&
-                (plan_only || it->second.buf.p)) {
-                s0 = j;
-                break;
-            }
+            return stores_ckpt(j, S) && it != ckpts_.end() && it->second.valid && (plan_only || it->second.buf.p);
+        };
+        for (size_t j = s_edit; j >= 1; --j) {
+            if (!usable(j) || segs_[j - 1].hi > L) continue;
+            // a sparse restore reads the checkpoints before it as well
+            bool chain = true;
+            if (opts.ckpt_delta)
+                for (size_t i = 1; i < j && chain; ++i) chain = usable(i);
+            if (!chain) continue;
+            s0 = j;
+            break;
         }
     }
     for (size_t j = 1; j < S; ++j) (void)slot_of(segs_[j - 1].anchor);
@@ -550,8 +640,51 @@ int Session::plan_update(bool force_full) {
     prep_renorm_ = renorm;
     int mode = full ? 1 : 2;
     BlockSet set;
-    if (!full && opts.closed_mode && !renorm && S > 0) {
+    if (!full && opts.closed_mode && !renorm && S > 0 && !opts.ckpt_delta) {
         if (try_closed(s0, s_edit, set) == QTASK_OK) mode = 3;
+    }
+    // sparse checkpoints: what each boundary will hold, and how the restart
+    // boundary's state is put together (when its own checkpoint holds only
+    // some blocks): each block from the newest checkpoint at or before it
+    // that holds the block, |0...0> where none does
+    prep_restore_.clear();
+    if (opts.ckpt_delta) {
+        for (size_t s = 0; s + 1 < S; ++s) (void)written_blocks(*plans_[s]);
+        if (s0 > 0) {
+            const Ckpt &top = ckpts_.at(segs_[s0 - 1].anchor);
+            if (!top.full) {
+                const int beta = std::min(opts.block_bits, n_int);
+                const uint64_t nblocks = uint64_t(1) << (n_int - beta);
+                BlockSet done(nblocks);
+                uint64_t left = nblocks;
+                for (size_t j = s0; j >= 1 && left > 0; --j) {
+                    const uint64_t a = segs_[j - 1].anchor;
+                    const Ckpt &ck = ckpts_.at(a);
+                    RestorePart part;
+                    part.anchor = a;
+                    if (ck.full) {
+                        for (uint64_t b = 0; b < nblocks; ++b)
+                            if (!done.test(b)) { part.dst.push_back(uint32_t(b)); part.src.push_back(uint32_t(b)); }
+                        left = 0;
+                    } else {
+                        for (size_t k = 0; k < ck.blocks.size(); ++k)
+                            if (!done.test(ck.blocks[k])) {
+                                done.set(ck.blocks[k]);
+                                part.dst.push_back(ck.blocks[k]);
+                                part.src.push_back(uint32_t(k));
+                                --left;
+                            }
+                    }
+                    if (!part.dst.empty()) prep_restore_.push_back(std::move(part));
+                }
+                if (left > 0) {
+                    RestorePart basis;
+                    for (uint64_t b = 0; b < nblocks; ++b)
+                        if (!done.test(b)) basis.dst.push_back(uint32_t(b));
+                    prep_restore_.push_back(std::move(basis));
+                }
+            }
+        }
     }
     prep_mode_ = mode;
     prep_s0_ = s0;
@@ -624,7 +757,13 @@ uint64_t Session::bytes_after_commit() const {
     const size_t S = segs_.size();
     uint64_t b = state_bytes();
     for (size_t j = 1; j < S; ++j)
-        if (stores_ckpt(j, S)) b += state_bytes();
+        if (stores_ckpt(j, S)) {
+            const CkptLayout L = layout_of(j);
+            b += L.bytes + (L.full ? 0 : L.blocks->size() * sizeof(uint32_t));
+        }
+    size_t restore = 0;
+    for (const auto &part : prep_restore_) restore += part.dst.size() + part.src.size();
+    b += std::max(restore, restore_cap_) * sizeof(uint32_t);
     std::unordered_set<uint64_t> live;
     for (const auto &sg : segs_)
         if (live.insert(sg.hash).second) b += plan_cache_.at(sg.hash).blob.size();
@@ -666,9 +805,17 @@ int Session::commit_device() {
         return p;
     };
     std::vector<std::pair<SegmentPlan *, void *>> plan_bufs;
-    std::vector<uint64_t> need_ckpt;   // stored boundaries without a buffer
-    std::vector<uint64_t> spare_ckpt;  // buffers of boundaries no longer stored
-    std::vector<void *> new_ckpt;
+    struct CkNew {
+        uint64_t anchor;
+        CkptLayout L;
+        void *buf = nullptr, *dbl = nullptr;
+        uint64_t spare = 0;  // take the buffer of this boundary (no longer stored)
+    };
+    std::vector<CkNew> cknew;          // stored boundaries that need a (new) buffer
+    std::vector<uint64_t> spare_ckpt;  // whole-state buffers of boundaries no longer stored
+    std::unordered_set<uint64_t> stored;
+    size_t restore_need = 0;
+    uint32_t *new_restore = nullptr;
     void *new_state = nullptr;
     double *new_scalars = nullptr, *new_partials = nullptr;
     unsigned long long *new_u64 = nullptr;
@@ -684,20 +831,33 @@ int Session::commit_device() {
             if (!p) return undo();
             plan_bufs.emplace_back(&sp, p);
         }
-        std::unordered_set<uint64_t> stored;
-        for (size_t j = 1; j < S; ++j)
-            if (stores_ckpt(j, S)) stored.insert(segs_[j - 1].anchor);
-        for (uint64_t a : stored) {
+        // checkpoints: a new buffer wherever a stored boundary has none or
+        // needs another layout (sparse checkpoints follow their segment's
+        // plan); whole-state buffers of boundaries no longer stored are
+        // reused first
+        for (size_t j = 1; j < S; ++j) {
+            if (!stores_ckpt(j, S)) continue;
+            const uint64_t a = segs_[j - 1].anchor;
+            stored.insert(a);
+            const CkptLayout L = layout_of(j);
             auto it = ckpts_.find(a);
-            if (it == ckpts_.end() || !it->second.buf.p) need_ckpt.push_back(a);
+            if (it == ckpts_.end() || !it->second.buf.p || it->second.wkey != L.wkey) cknew.push_back({a, L});
         }
         for (const auto &kv : ckpts_)
-            if (!stored.count(kv.first) && kv.second.buf.p) spare_ckpt.push_back(kv.first);
-        for (size_t i = spare_ckpt.size(); i < need_ckpt.size(); ++i) {
-            void *p = grab(state_bytes());
-            if (!p) return undo();
-            new_ckpt.push_back(p);
+            if (!stored.count(kv.first) && kv.second.buf.p && kv.second.full) spare_ckpt.push_back(kv.first);
+        size_t nspare = 0;
+        for (auto &cn : cknew) {
+            if (cn.L.full && nspare < spare_ckpt.size()) {
+                cn.spare = spare_ckpt[nspare++];
+                continue;
+            }
+            if (!(cn.buf = grab(cn.L.bytes))) return undo();
+            if (!cn.L.full && !(cn.dbl = grab(cn.L.blocks->size() * sizeof(uint32_t)))) return undo();
         }
+        for (const auto &part : prep_restore_) restore_need += part.dst.size() + part.src.size();
+        if (restore_need > restore_cap_ &&
+            !(new_restore = static_cast<uint32_t *>(grab(restore_need * sizeof(uint32_t)))))
+            return undo();
         if (!state_.p && !(new_state = grab(state_bytes()))) return undo();
         if (z.scalars && !(new_scalars = static_cast<double *>(grab(z.scalars * sizeof(double))))) return undo();
         if (z.partials && !(new_partials = static_cast<double *>(grab(z.partials * sizeof(double))))) return undo();
@@ -717,30 +877,55 @@ int Session::commit_device() {
             HIPCHK(hipMemcpyAsync(pb.second, pb.first->blob.data(), pb.first->blob.size(), hipMemcpyHostToDevice,
                                   stream));
         }
-        size_t nspare = 0, nfresh = 0;
-        for (uint64_t a : need_ckpt) {
-            Ckpt &ck = ckpts_[a];
-            if (nspare < spare_ckpt.size()) {
-                Ckpt &old = ckpts_.at(spare_ckpt[nspare++]);
+        std::vector<void *> drop;  // buffers replaced by another layout
+        for (auto &cn : cknew) {
+            Ckpt &ck = ckpts_[cn.anchor];
+            drop.push_back(ck.buf.p);
+            drop.push_back(ck.d_blocks.p);
+            if (cn.spare) {
+                Ckpt &old = ckpts_.at(cn.spare);
                 ck.buf = old.buf;
                 old.buf = DevBuf{};
             } else {
-                ck.buf.p = new_ckpt[nfresh++];
-                ck.buf.bytes = state_bytes();
+                ck.buf = DevBuf{cn.buf, size_t(cn.L.bytes)};
             }
+            ck.full = cn.L.full;
+            ck.wkey = cn.L.wkey;
+            ck.blocks = cn.L.full ? std::vector<uint32_t>() : *cn.L.blocks;
+            ck.d_blocks = cn.L.full ? DevBuf{} : DevBuf{cn.dbl, ck.blocks.size() * sizeof(uint32_t)};
+            if (!ck.blocks.empty())
+                HIPCHK(hipMemcpyAsync(ck.d_blocks.p, ck.blocks.data(), ck.d_blocks.bytes, hipMemcpyHostToDevice,
+                                      stream));
             ck.valid = false;
         }
         for (auto it = ckpts_.begin(); it != ckpts_.end();) {
-            bool keep = false;
-            for (size_t j = 1; j < S && !keep; ++j)
-                keep = segs_[j - 1].anchor == it->first && stores_ckpt(j, S);
-            if (!keep) {
+            if (!stored.count(it->first)) {
                 dfree(it->second.buf.p);
+                dfree(it->second.d_blocks.p);
                 it = ckpts_.erase(it);
             } else {
                 ++it;
             }
         }
+        if (new_restore) {
+            dfree(d_restore_);
+            d_restore_ = new_restore;
+            restore_cap_ = restore_need;
+        }
+        if (!prep_restore_.empty()) {
+            size_t off = 0;
+            for (const auto &part : prep_restore_) {
+                HIPCHK(hipMemcpyAsync(d_restore_ + off, part.dst.data(), part.dst.size() * sizeof(uint32_t),
+                                      hipMemcpyHostToDevice, stream));
+                off += part.dst.size();
+                if (!part.src.empty())
+                    HIPCHK(hipMemcpyAsync(d_restore_ + off, part.src.data(), part.src.size() * sizeof(uint32_t),
+                                          hipMemcpyHostToDevice, stream));
+                off += part.src.size();
+            }
+        }
+        HIPCHK(hipStreamSynchronize(stream));  // the block lists are pageable host memory
+        for (void *p : drop) dfree(p);
         if (new_state) {
             state_.p = new_state;
             state_.bytes = state_bytes();
@@ -797,7 +982,14 @@ int Session::commit_device() {
             it = keep ? std::next(it) : ckpts_.erase(it);
         }
         for (size_t j = 1; j < S; ++j)
-            if (stores_ckpt(j, S)) (void)ckpts_[segs_[j - 1].anchor];
+            if (stores_ckpt(j, S)) {
+                const CkptLayout L = layout_of(j);
+                Ckpt &ck = ckpts_[segs_[j - 1].anchor];
+                if (ck.wkey != L.wkey) ck.valid = false;
+                ck.full = L.full;
+                ck.wkey = L.wkey;
+                ck.blocks = L.full ? std::vector<uint32_t>() : *L.blocks;
+            }
     }
 
     // launch list
@@ -805,6 +997,27 @@ int Session::commit_device() {
     double bytes = 0, flops = 0, mfma_flops = 0;
     double *scales = plan_only ? nullptr : d_scalars_ + scalars_cap_ / 2;
     st.passes = st.stages = st.tiles = st.gate_amp_updates = 0;
+    const int beta = std::min(opts.block_bits, n_int);
+    const double block_bytes = double(uint64_t(1) << beta) * double(elem);
+    // a sparse restore first puts the restart boundary's state together in
+    // the state buffer, block by block from the checkpoints that hold it
+    {
+        size_t off = 0;
+        for (const auto &part : prep_restore_) {
+            Launch L{};
+            L.kind = 1;
+            L.cdst = state_.p;
+            L.csrc = part.anchor && !plan_only ? ckpts_.at(part.anchor).buf.p : nullptr;
+            L.cdst_idx = plan_only ? nullptr : d_restore_ + off;
+            off += part.dst.size();
+            L.csrc_idx = part.src.empty() || plan_only ? nullptr : d_restore_ + off;
+            off += part.src.size();
+            L.cn = uint32_t(part.dst.size());
+            L.b = beta;
+            launches.push_back(L);
+            bytes += double(part.dst.size()) * block_bytes * (part.anchor ? 2 : 1);
+        }
+    }
     for (size_t s = s0; s < S; ++s) {
         const SegmentPlan &sp = *plans_[s];
         const int b = sp.pp.b;
@@ -813,13 +1026,18 @@ int Session::commit_device() {
         const size_t P = sp.passes.size();
         const size_t end_slot = s + 1 < S ? slot_of(segs_[s].anchor) : 0;
         void *end_ckpt = nullptr;
-        if (s + 1 < S && stores_ckpt(s + 1, S) && !plan_only) end_ckpt = ckpts_.at(segs_[s].anchor).buf.p;
+        const Ckpt *end_ck = nullptr;
+        if (s + 1 < S && stores_ckpt(s + 1, S)) {
+            end_ck = &ckpts_.at(segs_[s].anchor);
+            if (!plan_only && end_ck->full) end_ckpt = end_ck->buf.p;  // a whole copy rides on the last pass
+        }
         for (size_t p = 0; p < P; ++p, ++li) {
             Launch L{};
             KArgs &a = L.args;
             a.dst = state_.p;
             if (s == s0 && p == 0) {
-                if (s0 == 0) { a.src_basis = 1; a.src = nullptr; }
+                if (!prep_restore_.empty()) a.src = state_.p;  // put together in place above
+                else if (s0 == 0) { a.src_basis = 1; a.src = nullptr; }
                 else a.src = plan_only ? nullptr : ckpts_.at(segs_[s0 - 1].anchor).buf.p;
             } else {
                 a.src = state_.p;
@@ -860,8 +1078,27 @@ int Session::commit_device() {
             }
             st.tiles += tiles;
         }
+        if (end_ck && !end_ck->full) {
+            // a sparse checkpoint: its blocks are copied out after the segment
+            Launch L{};
+            L.kind = 1;
+            L.cdst = plan_only ? nullptr : end_ck->buf.p;
+            L.csrc = state_.p;
+            L.csrc_idx = static_cast<const uint32_t *>(end_ck->d_blocks.p);
+            L.cn = uint32_t(end_ck->blocks.size());
+            L.b = beta;
+            launches.push_back(L);
+            bytes += 2.0 * double(end_ck->blocks.size()) * block_bytes;
+        }
         st.gate_amp_updates += sp.n_gates * (uint64_t(1) << n);
     }
+    st.ckpt_bytes = st.ckpt_full_bytes = 0;
+    for (size_t j = 1; j < S; ++j)
+        if (stores_ckpt(j, S)) {
+            const Ckpt &ck = ckpts_.at(segs_[j - 1].anchor);
+            st.ckpt_bytes += ck.full ? state_bytes() : uint64_t(ck.blocks.size()) * (uint64_t(1) << beta) * elem;
+            st.ckpt_full_bytes += state_bytes();
+        }
     if (renorm && S > 0) bytes += 2.0 * double(state_bytes());
     st.bytes = bytes;
     st.flops = flops;
@@ -912,6 +1149,10 @@ int Session::enqueue_final(hipStream_t s) {
 
 int Session::enqueue_prepared(hipStream_t s) {
     for (const Launch &L : launches) {
+        if (L.kind == 1) {
+            HIPCHK(launch_block_copy(dtype, L.cdst, L.csrc, L.cdst_idx, L.csrc_idx, L.cn, L.b, s));
+            continue;
+        }
         if (L.n_tiles > 0) HIPCHK(launch_pass(dtype, L.args, L.n_tiles, L.b, s));
         int rc = enqueue_after(L, s);
         if (rc != QTASK_OK) return rc;
@@ -1123,6 +1364,21 @@ int Session::dump(const char *path) {
     if (last.mode == 3) {
         const auto l = prep_set_.list();
         for (size_t i = 0; i < l.size() && i < 65536; ++i) o << (i ? "," : "") << l[i];
+    }
+    o << "],\"checkpoints\":[";
+    {
+        bool firstc = true;
+        for (size_t j = 1; j < segs_.size(); ++j) {
+            if (!stores_ckpt(j, segs_.size())) continue;
+            auto it = ckpts_.find(segs_[j - 1].anchor);
+            if (it == ckpts_.end()) continue;
+            o << (firstc ? "" : ",") << "{\"boundary\":" << j << ",\"level\":" << segs_[j - 1].hi
+              << ",\"valid\":" << (it->second.valid ? "true" : "false") << ",\"full\":"
+              << (it->second.full ? "true" : "false") << ",\"blocks\":[";
+            for (size_t k = 0; k < it->second.blocks.size(); ++k) o << (k ? "," : "") << it->second.blocks[k];
+            o << "]}";
+            firstc = false;
+        }
     }
     o << "],\"segments\":[";
     for (size_t s = 0; s < plans_.size(); ++s) {

@@ -79,12 +79,17 @@ public:
         launches.clear();
     }
     int prepare(bool force_full);           // plan_update + commit_device (no launches)
-    struct Launch {                          // one pass launch of the prepared replay
+    struct Launch {                          // one launch of the prepared replay
         KArgs args;
         uint32_t n_tiles;
         int b;
         int after;          // 0 none, 1 sum partials -> norm and renorm scale of `slot`
         size_t slot;
+        int kind = 0;       // 0 pass; 1 block copy (sparse checkpoint capture or restore)
+        void *cdst = nullptr;
+        const void *csrc = nullptr;
+        const uint32_t *cdst_idx = nullptr, *csrc_idx = nullptr;
+        uint32_t cn = 0;
     };
     std::vector<Launch> launches;            // filled by prepare()
     int finish_prepared_host();             // bookkeeping after the launches ran
@@ -127,10 +132,31 @@ private:
         uint64_t key = 0;      // ids and versions of the segment's levels
         uint64_t hash = 0;     // content hash (plan cache key)
     };
+    // A checkpoint holds the state at a segment boundary: the whole state,
+    // or (sparse checkpoints) only the blocks the segment before it can
+    // change, packed in the order of `blocks` (the others are as at the
+    // previous boundary).
     struct Ckpt {
         DevBuf buf;
         bool valid = false;
+        bool full = true;
+        uint64_t wkey = 0;             // identifies the block list (0: whole state)
+        std::vector<uint32_t> blocks;  // sparse: the blocks held, in buffer order
+        DevBuf d_blocks;               // sparse: the same list on the device
     };
+    // Layout a boundary's checkpoint gets from the plan of the segment
+    // before it (the whole state unless sparse checkpoints are on and the
+    // segment changes only some blocks).
+    struct CkptLayout {
+        bool full = true;
+        uint64_t wkey = 0;
+        const std::vector<uint32_t> *blocks = nullptr;
+        uint64_t bytes = 0;
+    };
+    CkptLayout layout_of(size_t j) const;
+    const std::vector<uint32_t> &written_blocks(const SegmentPlan &sp);
+    std::unordered_map<uint64_t, std::vector<uint32_t>> wsets_;  // plan hash -> blocks it can change (empty: all)
+    std::unordered_map<uint64_t, uint64_t> wkeys_;               // plan hash -> key of that list
     int K() const { return opts.ckpt_interval; }
     size_t num_segments() const { return (circ.num_levels() + size_t(K()) - 1) / size_t(K()); }
     bool stores_ckpt(size_t j, size_t S) const;
@@ -154,6 +180,7 @@ private:
     std::unordered_map<uint64_t, Ckpt> ckpts_;            // by anchor level id
     std::unordered_map<uint64_t, size_t> slots_;          // anchor -> norm/scale slot (0: circuit end)
     size_t next_slot_ = 1;
+    mutable size_t ckpt_stride_ = 1;   // every stride-th boundary stores a checkpoint (max_ckpts >= 1)
     bool state_valid_ = false;
     bool have_result_ = false;
 
@@ -178,6 +205,15 @@ private:
     bool prep_committed_ = false;           // committed: the launch list is the current replay
     uint64_t prep_need_bytes_ = 0;
     std::vector<size_t> prep_list_off_;     // closed replay: tile-list offset per pass launch
+    // sparse checkpoints: the state at the restart boundary put together
+    // from the newest checkpoint holding each block (or |0...0>)
+    struct RestorePart {
+        uint64_t anchor = 0;               // source checkpoint (0: |0...0>)
+        std::vector<uint32_t> dst, src;    // destination blocks, source blocks (buffer order)
+    };
+    std::vector<RestorePart> prep_restore_;
+    uint32_t *d_restore_ = nullptr;
+    size_t restore_cap_ = 0;               // uint32 entries
     size_t prep_s0_ = 0, prep_S_ = 0, prep_first_edit_ = 0;
     int prep_mode_ = 0;
     bool prep_renorm_ = false;

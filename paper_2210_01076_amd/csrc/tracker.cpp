@@ -128,6 +128,15 @@ void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std:
     }
 }
 
+bool rewrites_every_block(const LGate &g, int beta) {
+    switch (g.kop) {
+    case KOP_P1: case KOP_CX: return g.q[0] < beta;
+    case KOP_P2: case KOP_CCX: return g.q[0] < beta && g.q[1] < beta;
+    case KOP_SWAP: return !(g.q[0] >= beta && g.q[1] >= beta);
+    default: return true;
+    }
+}
+
 namespace {
 // Visit every group of 2^nh blocks that differ only in the gate's high bits:
 // f(blocks[2^nh]) with blocks[h] the block index whose high part is h.

@@ -63,6 +63,9 @@ BlockAction dense_action(const std::vector<int> &qubits, int beta);
 // rewrite only the amplitudes with their control/phase bits set, every other
 // op rewrites its whole support.  Calls f(block) for each such block.
 void for_rewritten_blocks(const LGate &g, int beta, uint64_t nblocks, const std::function<void(uint64_t)> &f);
+// True when for_rewritten_blocks would visit every block (no control or
+// phase bit at or above beta restricts the op).
+bool rewrites_every_block(const LGate &g, int beta);
 
 // d |= blocks coupled to d by the gate
 void propagate(const BlockAction &a, BlockSet &d);

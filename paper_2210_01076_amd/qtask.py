@@ -40,7 +40,7 @@ class qtask_opts(ctypes.Structure):
                 ("block_bits", i32), ("fusion", i32), ("fuse_width", i32), ("ckpt_interval", i32),
                 ("max_ckpts", i32), ("renorm", i32), ("autotune", i32), ("closed_mode", i32),
                 ("stream", ctypes.c_void_p), ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p),
-                ("alloc_ctx", ctypes.c_void_p), ("relabel", i32)]
+                ("alloc_ctx", ctypes.c_void_p), ("relabel", i32), ("ckpt_delta", i32)]
 
 
 class qtask_stats(ctypes.Structure):
@@ -50,7 +50,8 @@ class qtask_stats(ctypes.Structure):
                 ("gate_amp_updates", u64), ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
                 ("mfma_flops", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("pass_kernel_ms", ctypes.c_double),
-                ("plan_ms", ctypes.c_double), ("wall_ms", ctypes.c_double)]
+                ("plan_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("ckpt_bytes", u64),
+                ("ckpt_full_bytes", u64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "struct_size"}

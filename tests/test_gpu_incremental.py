@@ -204,11 +204,13 @@ def _edit_family(family, n, seed):
             ("x", "cx", "z", "cz", "t", "swap"))
 
 
-def _edit_sequence(n, nets, kinds, dtype, K, rng, steps):
+def _edit_sequence(n, nets, kinds, dtype, K, rng, steps, **opts):
     """Random gate and level inserts and removals; after every update the
     state must equal a full re-simulation bit for bit."""
     modes = []
-    with sim(n, nets, dtype, ckpt_interval=K, block_bits=4, tile_bits=8, low_bits=3) as s:
+    so = dict(ckpt_interval=K, block_bits=4, tile_bits=8, low_bits=3)
+    so.update(opts)
+    with sim(n, nets, dtype, **so) as s:
         s.update()
         for step in range(steps):
             r = rng.random()
@@ -251,6 +253,58 @@ def test_random_edit_sequences_stay_bitwise_equal(family, dtype, K):
     nets, kinds = _edit_family(family, 12, 0)
     modes = _edit_sequence(12, nets, kinds, dtype, K, rng, 60)
     log(family, dtype, "modes", {m: modes.count(m) for m in set(modes)})
+
+
+def _top_controlled_net(rng, n, kinds=("ccx", "cx", "cp", "cz", "t")):
+    """One gate that can change only the amplitudes whose top qubit is 1."""
+    kind = kinds[int(rng.integers(len(kinds)))]
+    if kind == "t":
+        return [(kind, (n - 1,), ())]
+    rest = [int(q) for q in rng.choice(n - 1, size=2 if kind == "ccx" else 1, replace=False)]
+    return [(kind, tuple([n - 1] + rest), (float(rng.uniform(0, 6)),) if kind == "cp" else ())]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sparse_checkpoints_store_changed_blocks_only(dtype):
+    """Sparse checkpoints on a circuit whose gates all hinge on the top qubit:
+    after the first segment each checkpoint holds the blocks its segment can
+    change (half of them), restarts compose the state from those deltas, and
+    every update equals a full re-simulation bit for bit and the oracle."""
+    n, bb = 16, 6
+    rng = np.random.default_rng(61)
+    nets = [[("h", (q,), ()) for q in range(n)]] + [_top_controlled_net(rng, n) for _ in range(40)]
+    # complex64 renormalisation rescales every block at each boundary: off here
+    with sim(n, nets, dtype, ckpt_interval=4, block_bits=bb, ckpt_delta=1, renorm=0) as s:
+        s.update()
+        st = s.stats()
+        assert 0 < st["ckpt_bytes"] < st["ckpt_full_bytes"]
+        firsts = []
+        for trial in range(8):
+            li = int(rng.integers(6, len(nets)))
+            if trial % 2 and nets[li]:
+                e = W.Edit("remove", li, pos=0)
+            else:
+                used = {q for g in nets[li] for q in g[1]}
+                q = [q for q in range(n - 1) if q not in used][int(rng.integers(4))]
+                e = W.Edit("insert", li, ("x", (q,), ()) if trial % 4 == 0 else ("rz", (q,), (0.3 + trial,)))
+            W.apply_edit(nets, e)
+            s.apply_edit(e)
+            s.update()
+            st = _check_incremental(s, nets, n, dtype)
+            firsts.append(st["first_level"])
+            log("sparse", dtype, trial, e, "mode", st["mode"], "first", st["first_level"],
+                "ckpt", st["ckpt_bytes"], "of", st["ckpt_full_bytes"])
+        assert max(firsts) > 0  # at least one update restarted from a composed checkpoint
+
+
+@pytest.mark.parametrize("family,dtype,K", [("arith", "c128", 2), ("arith", "c64", 3), ("ladder", "c128", 4),
+                                            ("layered", "c64", 3), ("dense", "c128", 2)])
+def test_sparse_checkpoint_edit_sequences_stay_bitwise_equal(family, dtype, K):
+    """The random edit sequences with sparse checkpoints on."""
+    rng = np.random.default_rng(zlib.crc32(("sparse/%s/%s/%d" % (family, dtype, K)).encode()))
+    nets, kinds = _edit_family(family, 12, 7)
+    modes = _edit_sequence(12, nets, kinds, dtype, K, rng, 40, ckpt_delta=1, block_bits=3)
+    log("sparse", family, dtype, "modes", {m: modes.count(m) for m in set(modes)})
 
 
 @pytest.mark.parametrize("seed", [28, 40, 78, 88, 209, 224, 293])
