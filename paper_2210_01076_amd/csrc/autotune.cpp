@@ -149,6 +149,7 @@ int Session::autotune() {
                     a.ops = reinterpret_cast<const KOp *>(blob + sp.off_op);
                     a.coefs = blob + sp.off_coef;
                     a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
+            a.has_dense = sp.passes[p].has_dense ? 1 : 0;
                     if (launch_pass(dtype, a, uint32_t(uint64_t(1) << (n_int - pp.b)), pp.b, stream) != hipSuccess)
                         r = QTASK_E_DEVICE;
                     first = false;

@@ -120,7 +120,7 @@ struct KArgs {
     uint32_t src_basis;        // 1: the input is |0...0> (src unused)
     uint32_t block_bits;       // store_mask granularity
     uint32_t has_mfma;         // the pass has matrix-core stages
-    uint32_t pad0;
+    uint32_t has_dense;        // the pass has dense 16x16 register ops (KOP_DENSE)
 };
 
 // Work item of the batched small-session launch.

@@ -335,7 +335,10 @@ __device__ __forceinline__ void op_phi(typename V2<R>::T (&a)[NR], Pending<R> &p
     default: F<3, R>(a, c, op.b, t, base); break;          \
     }
 
-template <typename R>
+// DN: the variant runs dense 16x16 register ops (the complex128 vector-ALU
+// kernel leaves them to the matrix-core variant: their 32 extra registers
+// would cost it a wave per SIMD)
+template <typename R, bool DN>
 __device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR], const R *__restrict__ c, uint32_t t,
                                          uint64_t base, Pending<R> &ph) {
     // the rotations and the CX of layered circuits first: a wave-uniform
@@ -352,7 +355,9 @@ __device__ __forceinline__ void apply_op(const KOp op, typename V2<R>::T (&a)[NR
         case KOP_X1: SW1(op_x1) break;
         case KOP_SWAP: SW2(op_swap) break;
         case KOP_CCX: SW3(op_ccx) break;
-        case KOP_DENSE: op_dense(a, c); break;
+        case KOP_DENSE:
+            if constexpr (DN) op_dense(a, c);
+            break;
         case KOP_P1: SW1(op_p1) break;
         case KOP_P2: SW2(op_p2) break;
         case KOP_GPH: op_gph<R>(a, c); break;
@@ -419,14 +424,14 @@ __device__ __forceinline__ StageHead stage_head(const KStage *__restrict__ S) {
 // ranges, so it is the next stage's first record.  Each record is loaded
 // before the previous op runs (the op array is followed by a spare record
 // inside the plan blob, so the read past the last op stays in bounds).
-template <typename R>
+template <typename R, bool DN>
 __device__ __forceinline__ void run_ops(const StageHead &h, const KOp *__restrict__ ops, const R *__restrict__ coefs,
                                         typename V2<R>::T (&a)[NR], KOp &op, uint32_t t, uint64_t base,
                                         Pending<R> &ph) {
     const uint32_t oe = h.op_begin + h.op_count;
     for (uint32_t oi = h.op_begin; oi < oe; ++oi) {
         const KOp nx = ops[oi + 1];
-        apply_op<R>(op, a, coefs + op.coef, t, base, ph);
+        apply_op<R, DN>(op, a, coefs + op.coef, t, base, ph);
         op = nx;
     }
 }
@@ -635,6 +640,16 @@ __device__ __forceinline__ uint64_t tile_origin(const TileRuns &tr, uint32_t til
     return base;
 }
 
+// Whether the kernel exchanges a tile between stages as real parts, then
+// imaginary parts, through an LDS area of 2^b values instead of 2^b complex
+// values (the complex128 vector-ALU kernel: its LDS per tile halves, so more
+// workgroups fit on a CU).
+template <typename R, bool MF> constexpr bool split_lds() { return sizeof(R) == 8 && !MF; }
+
+// Whether a pass kernel variant runs dense 16x16 register ops (KOP_DENSE);
+// passes with such ops go to the matrix-core variant in complex128.
+template <typename R, bool MF> constexpr bool dense_ops() { return MF || sizeof(R) == 4; }
+
 // One tile (number idx of the pass, or tile_list[idx]).  The first stage's
 // registers come straight from global memory, the middle stages go through
 // LDS, the last stage's registers go straight back to global memory.
@@ -659,6 +674,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     // from global memory, the others from LDS; every stage but the last
     // scatters back to LDS.  (One call site keeps the amplitude registers
     // in place across the whole pass.)
+    constexpr bool SPLIT = split_lds<R, MF>();
     C a[NR];
     Pending<R> ph{R(1), R(0), false};
     KOp op = ops[S0->op_begin];
@@ -696,7 +712,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
                     for (int i = 0; i < NR; ++i) { a[i].x *= sc; a[i].y *= sc; }
                 }
             }
-        } else {
+        } else if (!SPLIT) {
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 const C y = lds[sl[i]];
@@ -704,8 +720,32 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
                 a[i].y = y.y;
             }
         }
-        run_ops<R>(h, ops, coefs, a, op, t, base, ph);
+        run_ops<R, dense_ops<R, MF>()>(h, ops, coefs, a, op, t, base, ph);
         if (si + 1 == ns) break;
+        if constexpr (SPLIT) {
+            // real parts, then imaginary parts, through half the LDS: each
+            // thread writes its slots of this stage and reads its slots of
+            // the next; the barrier between a read and the next write keeps
+            // a slot from being overwritten before its reader has it
+            asm volatile("" : "+v"(bt));
+            reg_slots(h, bt, sl);
+            const StageHead h2 = stage_head(S + 1);
+            uint32_t sl2[NR];
+            reg_slots(h2, thr_lds(h2, t), sl2);
+            R *lr = reinterpret_cast<R *>(lds);
+#pragma unroll
+            for (int i = 0; i < NR; ++i) lr[sl[i]] = a[i].x;
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < NR; ++i) a[i].x = lr[sl2[i]];
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < NR; ++i) lr[sl[i]] = a[i].y;
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < NR; ++i) a[i].y = lr[sl2[i]];
+            continue;
+        }
         // complex128: recompute the slots instead of keeping them live across
         // the op loop (16 fewer registers; see the kernel's occupancy hint)
         if constexpr (sizeof(R) == 8) {
@@ -781,12 +821,13 @@ qk_pass(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass, 
                      src_basis, block_bits, reinterpret_cast<C *>(smem));
 }
 
-// The complex128 vector-ALU kernel asks for at least three waves per SIMD:
-// its body then fits 168 registers without spilling (two waves otherwise).
-// The matrix-core variants would spill under the same limit and keep the
+// The complex128 vector-ALU kernel asks for four waves per SIMD (128
+// registers; a few values of the tile setup then live in scratch, outside
+// the op loop), which its half-size LDS exchange leaves room for.  The
+// matrix-core variants would spill under the same limit and keep the
 // default.
 template <>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 qk_pass<double, false>(void *dst, const void *src, void *ckpt, const KPass *__restrict__ pass,
                        const KStage *__restrict__ stages, const KOp *__restrict__ ops,
                        const double *__restrict__ coefs, const uint32_t *__restrict__ tile_list,
@@ -1056,7 +1097,7 @@ uint32_t fill_grid(uint64_t n) {
 template <typename R, bool MF>
 hipError_t launch_pass_t(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
     const uint32_t threads = 1u << (b - QK_G);
-    const size_t lds = (size_t(1) << b) * sizeof(typename V2<R>::T);
+    const size_t lds = (size_t(1) << b) * (split_lds<R, MF>() ? sizeof(R) : sizeof(typename V2<R>::T));
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<R, MF>), lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((qk_pass<R, MF>), dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
@@ -1068,7 +1109,7 @@ hipError_t launch_pass_t(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s)
 hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
     (void)hipGetLastError();  // start from a clean error state
     if (n_tiles == 0) return hipSuccess;
-    if (a.has_mfma)
+    if (a.has_mfma || (dtype == 0 && a.has_dense))
         return dtype == 0 ? launch_pass_t<double, true>(a, n_tiles, b, s) : launch_pass_t<float, true>(a, n_tiles, b, s);
     return dtype == 0 ? launch_pass_t<double, false>(a, n_tiles, b, s) : launch_pass_t<float, false>(a, n_tiles, b, s);
 }

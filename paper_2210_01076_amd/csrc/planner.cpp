@@ -361,7 +361,10 @@ struct Packer {
         if (ps.stages.back().mfma || (ps.stages.size() > 1 && touches(ps.stages.back(), low_out)) ||
             (ps.stages.size() == 1 && ps.relabels()))
             ps.stages.push_back(empty_stage(low_out));
-        for (const auto &st : ps.stages) ps.has_mfma = ps.has_mfma || st.mfma;
+        for (const auto &st : ps.stages) {
+            ps.has_mfma = ps.has_mfma || st.mfma;
+            ps.has_dense = ps.has_dense || (!st.mfma && !st.U.empty());
+        }
         // their lowest lane bits are those tile bits, in order (what
         // coalescing needs); the next ones are chosen for the banks
         for (int which = 0; which < 2; ++which) {

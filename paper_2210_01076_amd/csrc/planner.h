@@ -46,6 +46,7 @@ struct PPass {
     uint64_t qmask = 0;
     int n_gates = 0;          // source gates applied in this pass
     bool has_mfma = false;    // some stage runs on the matrix cores
+    bool has_dense = false;   // some stage is a dense 16x16 op on registers
     bool relabels() const { return !out.empty() && out != qlist; }
     int out_pos(int p) const { return out.empty() ? qlist[size_t(p)] : out[size_t(p)]; }
 };

@@ -321,7 +321,9 @@ int qtask_server_s::start_small_tick(std::vector<int32_t> &ready, std::vector<in
     ready.swap(rest);
     if (b < 0) b = QK_MIN_TILE_BITS;  // no pass work in this tick
     const uint32_t threads = 1u << (b - QK_G);
-    const uint32_t lds = (1u << b) * (dtype == QTASK_C128 ? 16u : 8u);
+    // 8 bytes per amplitude: a complex64 value, or one part of a complex128
+    // value (the complex128 kernel exchanges real and imaginary parts in turn)
+    const uint32_t lds = (1u << b) * 8u;
     size_t max_rounds = 0;
     uint32_t max_groups = 1;
     for (int32_t sid : group) {
@@ -551,7 +553,7 @@ void qtask_server_s::run() {
             // stages: other plans (and sparse-checkpoint copies) run on the
             // session's own stream
             bool own = ss.s->opts.ckpt_delta != 0;
-            for (const auto &l : ss.s->launches) own = own || l.args.has_mfma || l.kind != 0;
+            for (const auto &l : ss.s->launches) own = own || l.args.has_mfma || l.args.has_dense || l.kind != 0;
             ss.batched = ss.small && !own;
             if (ss.batched) {
                 // plan uploads went to the session's stream

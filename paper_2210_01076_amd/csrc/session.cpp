@@ -1052,6 +1052,7 @@ int Session::commit_device() {
             a.coefs = blob + sp.off_coef;
             a.block_bits = uint32_t(std::min(opts.block_bits, n_int));
             a.has_mfma = sp.passes[p].has_mfma ? 1 : 0;
+            a.has_dense = sp.passes[p].has_dense ? 1 : 0;
             uint64_t tiles = full_tiles;
             if (mode == 3) {
                 tiles = prep_list_off_[li + 1] - prep_list_off_[li];
