@@ -455,14 +455,15 @@ def run_large(Q, W, n=28, levels=100, dtype="c128"):
             "tile_bits": o.tile_bits, "low_bits": o.low_bits}
 
 
-HEADLINE = dict(n=32, levels=500, ckpt_nets=150, max_ckpts=3, tile_bits=12, low_bits=5)
+HEADLINE = dict(n=32, levels=500, ckpt_nets=150, max_ckpts=3, tile_bits=12, low_bits=4)
 
 
-def run_headline(Q, W, steps, warmup, tile_bits=None, low_bits=None, levels=None, verify_edits=2):
+def run_headline(Q, W, steps, warmup, tile_bits=None, low_bits=None, levels=None, verify_edits=1):
     """Configuration 5, the headline: 32 qubits in complex128 (a 64 GiB state
-    and three 64 GiB checkpoints, one per 50-level segment boundary that
-    fits: levels 125, 250 and 375 of 500), 500 levels of RX/RY/RZ on every
-    qubit plus controlled-phase ladders on even and odd adjacent pairs.
+    and three 64 GiB checkpoints: of the segment boundaries every 50 levels,
+    every third one is stored, at levels 150, 300 and 450 of 500), 500
+    levels of RX/RY/RZ on every qubit plus controlled-phase ladders on even
+    and odd adjacent pairs.
 
     After the first (full) simulation, `warmup` untimed steps insert a gate
     in the circuit's last segment; then `steps` timed steps each insert one
@@ -740,10 +741,13 @@ def main():
                     help="only the 32-qubit headline (profiling runs)")
     ap.add_argument("--headline-levels", type=int, default=0,
                     help="depth of the headline circuit (default 500; profiling runs may shorten it)")
-    ap.add_argument("--verify-edits", type=int, default=2,
+    ap.add_argument("--verify-edits", type=int, default=1,
                     help="headline edits after the timed steps that are each compared with a full re-simulation")
     ap.add_argument("--tile-bits", type=int, default=0, help="headline tile bits (default 12)")
-    ap.add_argument("--low-bits", type=int, default=0, help="headline contiguous low bits (default 5)")
+    ap.add_argument("--low-bits", type=int, default=0, help="headline contiguous low bits (default 4)")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-clock budget: the legs after the headline that would not fit are skipped "
+                         "(and named in the line)")
     ap.add_argument("--extras", action="store_true",
                     help="instead of the default run: the 28-qubit state, the paper's other incremental "
                          "protocols and the 30-qubit fused-unitary legs, printed as one JSON line")
@@ -791,11 +795,40 @@ def main():
     small = None
     serving = None
     cpu = None
+    skipped = []
+
+    def fits(name, est_s):
+        """Whether a leg estimated at est_s seconds still fits the wall budget."""
+        if time.perf_counter() - t_start + est_s <= args.budget_s:
+            return True
+        skipped.append(name)
+        log("skipping %s: %.0f s used of the %.0f s budget" % (name, time.perf_counter() - t_start, args.budget_s))
+        return False
+
     if not args.headline_only:
-        small = run_small(Q, W)
-        log("10-qubit circuit: update p50 %.0f us p99 %.0f us, full re-simulation p50 %.0f us, mismatches %d" % (
-            small["update_us_p50"], small["update_us_p99"], small["full_us_p50"], small["mismatches"]))
-        if not args.no_tier24:
+        if not args.no_cpu and fits("cpu_baseline", 40):
+            per_gate = head["full_bytes"] / W.count_gates(W.config(5, levels=head["levels"], batches=1).nets)
+            cpu = cpu_baseline(Q, W, per_gate)
+            log("cpu oracle: %.2f GB/s equivalent on %d threads; device vs oracle max-abs %.2e" % (
+                cpu["value"], cpu["cores"], cpu["max_abs_device_c128_vs_oracle"]))
+        if fits("small_circuit", 10):
+            small = run_small(Q, W)
+            log("10-qubit circuit: update p50 %.0f us p99 %.0f us, full re-simulation p50 %.0f us, mismatches %d" % (
+                small["update_us_p50"], small["update_us_p99"], small["full_us_p50"], small["mismatches"]))
+        if not args.no_serving and fits("serving", 80):
+            import numpy as np
+            s128, kept128 = run_serving_curve(Q, W, "c128", [11, 20])
+            s64, kept64 = run_serving_curve(Q, W, "c64", [23, 41])
+            errs = [float(np.max(np.abs(kept128[i] - kept64[i].astype(np.complex128)))) for i in kept128
+                    if i in kept64]
+            s64["max_abs_vs_c128"] = max(errs) if errs else None
+            s64["compared_sessions"] = len(errs)
+            serving = {"workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels; "
+                                   "requests of 1-3 edits: Poisson streams at about 50% and 90% of the saturated "
+                                   "rate over 128 sessions each, then one request to every session at once; "
+                                   "sessions under 16 qubits batched",
+                       "c128": s128, "c64": s64}
+        if not args.no_tier24 and fits("tier24", 10 + 1.5 * (args.steps + args.warmup)):
             import numpy as np
             wl = W.config(2)
             sim128, _, r128 = run_tier(Q, W, wl, "c128", args.steps, args.warmup)
@@ -813,24 +846,6 @@ def main():
                       "batches": args.steps, "ckpt_levels": wl.ckpt_nets // 2, "c128": r128, "c64": r64}
             log("24-qubit tier: c128 update p50 %.1f ms vs full %.1f ms; c64 %.1f ms vs %.1f ms" % (
                 r128["inc_ms_p50"], r128["full_ms_p50"], r64["inc_ms_p50"], r64["full_ms_p50"]))
-        if not args.no_serving:
-            import numpy as np
-            s128, kept128 = run_serving_curve(Q, W, "c128", [11, 20])
-            s64, kept64 = run_serving_curve(Q, W, "c64", [23, 41])
-            errs = [float(np.max(np.abs(kept128[i] - kept64[i].astype(np.complex128)))) for i in kept128
-                    if i in kept64]
-            s64["max_abs_vs_c128"] = max(errs) if errs else None
-            s64["compared_sessions"] = len(errs)
-            serving = {"workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels; "
-                                   "requests of 1-3 edits: Poisson streams at about 50% and 90% of the saturated "
-                                   "rate over 128 sessions each, then one request to every session at once; "
-                                   "sessions under 16 qubits batched",
-                       "c128": s128, "c64": s64}
-        if not args.no_cpu:
-            per_gate = head["full_bytes"] / W.count_gates(W.config(5, levels=head["levels"], batches=1).nets)
-            cpu = cpu_baseline(Q, W, per_gate)
-            log("cpu oracle: %.2f GB/s equivalent on %d threads; device vs oracle max-abs %.2e" % (
-                cpu["value"], cpu["cores"], cpu["max_abs_device_c128_vs_oracle"]))
 
     achieved = head["launch_bytes"] / (head["launch_ms"] * 1e-3) / 1e9
     b = head["tile_bits"]
@@ -875,6 +890,7 @@ def main():
         "small_circuit": small,
         "serving": serving,
         "cpu_baseline": cpu,
+        "skipped_for_budget": skipped,
         "run_s": time.perf_counter() - t_start,
     }
     print(json.dumps(line))
