@@ -43,6 +43,7 @@ public:
 
     const Level &level_by_index(size_t i) const { return levels_.at(order_[i]); }
     const Gate &gate(uint64_t id) const { return gates_.at(id); }
+    bool has_gate(uint64_t id) const { return gates_.count(id) != 0; }
 
     // Index of the first level modified since the last clear_edits();
     // SIZE_MAX when nothing changed.  Every level at or after it may differ.

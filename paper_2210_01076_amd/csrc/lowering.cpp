@@ -77,7 +77,7 @@ std::vector<cd> kind_matrix(int kind, const double *p) {
     return m;
 }
 
-static void push(std::vector<double> &v, cd z) {
+static void push(SmallVec<double, 8> &v, cd z) {
     v.push_back(z.real());
     v.push_back(z.imag());
 }

@@ -138,7 +138,15 @@ std::vector<LGate> Session::level_ops(size_t lo, size_t hi) const {
             const int lb = *std::min_element(b->q, b->q + b->nq);
             return la < lb;
         });
-        for (const Gate *g : gs) ops.push_back(lower_gate(g->kind, g->q, g->p, g->id));
+        for (const Gate *g : gs) {
+            auto it = lowered_.find(g->id);
+            if (it == lowered_.end()) it = lowered_.emplace(g->id, lower_gate(g->kind, g->q, g->p, g->id)).first;
+            ops.push_back(it->second);
+        }
+    }
+    if (lowered_.size() > 2 * circ.num_gates() + 1024) {
+        for (auto it = lowered_.begin(); it != lowered_.end();)
+            it = circ.has_gate(it->first) ? std::next(it) : lowered_.erase(it);
     }
     return ops;
 }

@@ -172,6 +172,10 @@ private:
     std::vector<SegmentPlan *> plans_;                    // plan of segs_[s]
     std::unordered_map<uint64_t, SegmentPlan> plan_cache_;  // by content hash
     std::unordered_map<uint64_t, uint64_t> key_hash_;       // segment key -> content hash
+    // lowered gates by gate id (ids are never reused; lowering is a pure
+    // function of kind, qubits and parameters); pruned when it outgrows the
+    // circuit
+    mutable std::unordered_map<uint64_t, LGate> lowered_;
     std::vector<uint64_t> prev_hashes_;                   // segment hashes at the last update
     std::vector<uint64_t> prev_anchors_;                  // segment end anchors at the last update
     std::unordered_set<uint64_t> anchors_;
