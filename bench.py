@@ -630,6 +630,59 @@ def run_fused(Q, W, n=30, levels=300, k=5, tile_bits=11, low_bits=4, sample=1 <<
     return out
 
 
+def run_fusion_wins(Q, W, n=28, levels=96):
+    """Dense fusion where it pays: the blocked family (blocks of 5 adjacent
+    qubits, RX/RY/RZ on every qubit and CZ inside the blocks each level, a
+    CNOT between neighbouring blocks every 16 levels) at 28 qubits.  Each
+    dtype runs twice with the autotuner choosing the tile shape: once with
+    gate lists only (QTASK_FUSE_NONE) and once under QTASK_FUSE_AUTO, where
+    it may also fuse every stage into a dense k-qubit unitary on the matrix
+    cores.  Full simulations (best of two re-runs after the tuned first
+    one); the results of the two plans are compared amplitude by amplitude,
+    and complex64 against the complex128 gate-list result."""
+    import numpy as np
+
+    nets = W.blocked_circuit(n, levels, 7)
+    out = {"workload": "blocked circuit, %d qubits, %d levels (blocks of 5 adjacent qubits; each level RX/RY/RZ on "
+                       "every qubit then CZ on even and odd pairs inside each block; a CNOT between neighbouring "
+                       "blocks every 16 levels)" % (n, levels), "qubits": n, "levels": levels}
+    states = {}
+    for dt in ("c128", "c64"):
+        r = {}
+        for name, fusion in (("lists", Q.QTASK_FUSE_NONE), ("auto", Q.QTASK_FUSE_AUTO)):
+            s = Q.Simulator(n, dt, device=0, ckpt_interval=10 ** 6, autotune=1, fusion=fusion)
+            try:
+                s.build(nets)
+                s.update()
+                best = None
+                for _ in range(2):
+                    st = s.update(full=True)
+                    if best is None or st["kernel_ms"] < best["kernel_ms"]:
+                        best = st
+                o = Q.qtask_get_opts(s.h)
+                states[(dt, name)] = s.state()
+            finally:
+                s.close()
+            r[name] = {"full_ms": best["kernel_ms"], "passes": best["passes"], "tile_bits": o.tile_bits,
+                       "low_bits": o.low_bits, "fusion": {0: "auto", 1: "none", 2: "dense"}[o.fusion],
+                       "fuse_width": o.fuse_width,
+                       "mfma_tflops": best["mfma_flops"] / (best["kernel_ms"] * 1e-3) / 1e12,
+                       "frac_of_mfma_peak": best["mfma_flops"] / (best["kernel_ms"] * 1e-3) / 1e12 /
+                                            MFMA_PEAK_TFLOPS[dt]}
+        r["speedup_auto_over_lists"] = r["lists"]["full_ms"] / r["auto"]["full_ms"]
+        a = states[(dt, "lists")].astype(np.complex128)
+        b = states[(dt, "auto")].astype(np.complex128)
+        r["max_abs_auto_vs_lists"] = float(np.max(np.abs(a - b)))
+        out[dt] = r
+        log("blocked %d qubits %s: gate lists %.1f ms (b=%d c=%d), auto %.1f ms (%s k=%d b=%d, %.1f TFLOP/s), "
+            "%.2fx" % (n, dt, r["lists"]["full_ms"], r["lists"]["tile_bits"], r["lists"]["low_bits"],
+                       r["auto"]["full_ms"], r["auto"]["fusion"], r["auto"]["fuse_width"], r["auto"]["tile_bits"],
+                       r["auto"]["mfma_tflops"], r["speedup_auto_over_lists"]))
+    ref = states[("c128", "lists")]
+    out["c64"]["max_abs_auto_vs_c128"] = float(np.max(np.abs(states[("c64", "auto")].astype(np.complex128) - ref)))
+    return out
+
+
 def cpu_baseline(Q, W, full_bytes_per_gate, min_s=10.0):
     """The CPU oracle (all host threads, then one) on a bounded sample of the
     headline workload: the 32-qubit circuit's first gates, one at a time,
@@ -804,6 +857,7 @@ def main():
     small = None
     serving = None
     cpu = None
+    fusion_wins = None
     skipped = []
 
     def fits(name, est_s):
@@ -839,6 +893,8 @@ def main():
                                    "rate over 128 sessions each, then one request to every session at once; "
                                    "sessions under 16 qubits batched",
                        "c128": s128, "c64": s64}
+        if fits("fusion_wins", 40):
+            fusion_wins = run_fusion_wins(Q, W)
         if not args.no_tier24 and fits("tier24", 10 + 1.5 * (args.steps + args.warmup)):
             import numpy as np
             wl = W.config(2)
@@ -898,6 +954,7 @@ def main():
                      "block": 1 << (b - 4),
                      "scope": "every pass launch of the timed steps (32 qubits, complex128)"},
         "tier24": tier24,
+        "fusion_wins": fusion_wins,
         "small_circuit": small,
         "serving": serving,
         "cpu_baseline": cpu,

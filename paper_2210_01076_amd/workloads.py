@@ -126,6 +126,56 @@ def cp_ladder_circuit(n: int, levels: int, seed: int) -> List[Net]:
     return nets
 
 
+def brickwork_circuit(n: int, layers: int, seed: int) -> List[Net]:
+    """Random two-qubit unitaries on adjacent pairs, in bricks: even pairs
+    (0,1), (2,3), ... in even layers, odd pairs (1,2), (3,4), ... in odd
+    layers.  Each brick is a generic two-qubit unitary written with
+    rotations and CNOTs (Z-Y-Z rotations on both qubits, three CNOTs
+    alternating in direction with RY/RZ between them, Z-Y-Z rotations
+    again), uniform angles; the bricks of a layer run in parallel, 9 nets
+    per layer.  Many non-diagonal gates act on few qubits between their
+    couplings to the rest: the workload where dense fusion pays."""
+    rng = np.random.default_rng(seed)
+    nets: List[Net] = []
+
+    def zyz(qs):
+        return [[_gate(rng, k, (q,)) for q in qs] for k in ("rz", "ry", "rz")]
+
+    for layer in range(layers):
+        pairs = [(q, q + 1) for q in range(layer % 2, n - 1, 2)]
+        lo = [q for a, b in pairs for q in (a, b)]
+        body: List[Net] = zyz(lo)
+        body.append([("cx", (a, b), ()) for a, b in pairs])
+        body.append([g for a, b in pairs for g in (_gate(rng, "ry", (a,)), _gate(rng, "rz", (b,)))])
+        body.append([("cx", (b, a), ()) for a, b in pairs])
+        body.append([_gate(rng, "ry", (a,)) for a, b in pairs])
+        body.append([("cx", (a, b), ()) for a, b in pairs])
+        body += zyz(lo)
+        nets.extend(body)
+    return nets
+
+
+def blocked_circuit(n: int, levels: int, seed: int, block: int = 5, mix_every: int = 16) -> List[Net]:
+    """Qubits in blocks of `block` neighbours.  Each level: a random RX/RY/RZ
+    on every qubit, then CZ on the even and then the odd adjacent pairs
+    inside each block; every `mix_every` levels a CNOT joins each block's
+    last qubit to the next block's first.  Blocks evolve on their own for
+    long stretches, as in circuits built from subsystem unitaries with
+    sparse couplings: a dense unitary over one block absorbs many levels."""
+    rng = np.random.default_rng(seed)
+    nets: List[Net] = []
+    starts = list(range(0, n, block))
+    for lv in range(levels):
+        nets.append([_gate(rng, ("rx", "ry", "rz")[int(rng.integers(3))], (q,)) for q in range(n)])
+        for par in (0, 1):
+            net = [("cz", (q, q + 1), ()) for s0 in starts for q in range(s0 + par, min(s0 + block, n) - 1, 2)]
+            if net:
+                nets.append(net)
+        if (lv + 1) % mix_every == 0:
+            nets.append([("cx", (s0 + block - 1, s0 + block), ()) for s0 in starts if s0 + block < n])
+    return nets
+
+
 def ghz_circuit(n: int) -> List[Net]:
     """H on the top qubit, then a CNOT chain from it to every other qubit."""
     top = n - 1

@@ -78,3 +78,34 @@ def test_ladder_edits_inside_and_across_tiles_against_oracle():
             log("ladder edit %d %s on %s: mode %d from net %d" % (i, batch[0].gate[0], qs, st["mode"],
                                                                  st["first_level"]))
         check_state(s.state(), oracle.simulate(N, nets, nthreads=oracle.max_threads()), "c128", "ladder")
+
+
+def _blocked_oracle():
+    if "blocked" not in _cache:
+        nets = W.blocked_circuit(N, 40, 7)
+        _cache["blocked"] = (nets, oracle.simulate(N, nets, nthreads=oracle.max_threads()))
+    return _cache["blocked"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("plan", ["dense5", "auto"])
+def test_blocked_circuit_fused_against_oracle(dtype, plan):
+    """The blocked family (blocks of 5 adjacent qubits coupled every 16
+    levels; the circuit whose dense fusion beats its gate lists at 28
+    qubits), 40 levels at 24 qubits: every stage fused into a dense 5-qubit
+    unitary on the matrix cores, and the plan the autotuner picks under
+    automatic fusion, each against the oracle over the whole state."""
+    nets, want = _blocked_oracle()
+    if plan == "dense5":
+        opts = dict(tile_bits=11, low_bits=4, fusion=Q.QTASK_FUSE_DENSE, fuse_width=5, ckpt_interval=60)
+    else:
+        opts = dict(autotune=1, fusion=Q.QTASK_FUSE_AUTO, ckpt_interval=60)
+    with sim(N, nets, dtype, **opts) as s:
+        st = s.update()
+        if plan == "dense5":
+            assert st["mfma_flops"] > 0
+        o = Q.qtask_get_opts(s.h)
+        got = s.state()
+        err = check_state(got, want, dtype, "blocked %s %s" % (plan, dtype))
+        log("blocked n=%d %s %s: fusion %d k=%d b=%d c=%d, max-abs %.3e (%d passes)" % (
+            N, plan, dtype, o.fusion, o.fuse_width, o.tile_bits, o.low_bits, err, st["passes"]))
