@@ -683,6 +683,85 @@ def run_fusion_wins(Q, W, n=28, levels=96):
     return out
 
 
+def run_sparse_ckpt(Q, W, n=24, levels=400, interval=20, full_ckpts=4, edits=20):
+    """Sparse checkpoints (the paper's copy-on-write blocks) at a fixed
+    checkpoint budget.  The top-controlled circuit (each level changes only
+    the blocks whose top bit is 1) runs in two sessions with a checkpoint
+    boundary every `interval` levels: one storing whole copies, at most
+    `full_ckpts` of them; one storing each boundary's rewritable blocks, with
+    as many boundaries as fit in the same bytes.  The same random
+    single-gate inserts go to both; each update is compared with the other
+    session's by state hash, and the restart levels and update times are
+    reported.  The layered circuit's ratio of stored to whole-copy bytes is
+    given beside it (every segment rewrites every block there)."""
+    rng = __import__("numpy").random.default_rng(808)
+    nets = W.top_controlled_circuit(n, levels, 17)
+    out = {"workload": "top-controlled circuit, %d qubits, %d levels (an H layer, then one CX/CCX/CP/CZ per level "
+                       "on the top qubit and qubits below it), complex128, a checkpoint boundary every %d levels, "
+                       "%d random single-gate inserts" % (n, levels, interval, edits)}
+    a = Q.Simulator(n, "c128", device=0, ckpt_interval=interval, max_ckpts=full_ckpts)
+    try:
+        a.build(nets)
+        sa = a.update()
+        ratio = sa["ckpt_bytes"] / max(sa["ckpt_full_bytes"], 1)
+        b_probe = Q.Simulator(n, "c128", device=0, ckpt_interval=interval, ckpt_delta=1, max_ckpts=1 << 20)
+        try:
+            b_probe.build(nets)
+            sp = b_probe.update()
+            delta_ratio = sp["ckpt_bytes"] / max(sp["ckpt_full_bytes"], 1)
+        finally:
+            b_probe.close()
+        k_delta = max(full_ckpts, int(full_ckpts / max(delta_ratio, 1e-9)))
+        b = Q.Simulator(n, "c128", device=0, ckpt_interval=interval, ckpt_delta=1, max_ckpts=k_delta)
+        try:
+            b.build(nets)
+            sb = b.update()
+            rows, mism = [], 0
+            work = [list(x) for x in nets]
+            for i in range(edits):
+                li = int(rng.integers(1, len(work)))
+                used = {q for g in work[li] for q in g[1]}
+                free = [q for q in range(n - 1) if q not in used]
+                g = ("cx", (n - 1, free[int(rng.integers(len(free)))]), ()) if n - 1 not in used else \
+                    ("t", (free[int(rng.integers(len(free)))],), ())
+                e = W.Edit("insert", li, g)
+                W.apply_edit(work, e)
+                a.apply_edit(e)
+                b.apply_edit(e)
+                ra, rb = a.update(), b.update()
+                mism += int(a.hash() != b.hash())
+                rows.append((ra["first_level"], rb["first_level"], ra["wall_ms"], rb["wall_ms"]))
+            hb = b.hash()
+            b.update(full=True)
+            mism += int(b.hash() != hb)
+            out.update({
+                "ckpt_bytes_full_copies": sa["ckpt_bytes"], "ckpts_full": full_ckpts,
+                "ckpt_bytes_sparse": sb["ckpt_bytes"], "ckpt_full_bytes_sparse_session": sb["ckpt_full_bytes"],
+                "ckpts_sparse": k_delta, "stored_over_whole_copy_bytes": delta_ratio,
+                "restart_level_mean_full": sum(r[0] for r in rows) / len(rows),
+                "restart_level_mean_sparse": sum(r[1] for r in rows) / len(rows),
+                "update_ms_p50_full": pct([r[2] for r in rows], 50),
+                "update_ms_p50_sparse": pct([r[3] for r in rows], 50),
+                "mismatches": mism})
+        finally:
+            b.close()
+    finally:
+        a.close()
+    lay = Q.Simulator(n, "c128", device=0, ckpt_interval=100, ckpt_delta=1)
+    try:
+        lay.build(W.config(2, n=n, levels=100, batches=1).nets)
+        sl = lay.update()
+        out["layered_stored_over_whole_copy_bytes"] = sl["ckpt_bytes"] / max(sl["ckpt_full_bytes"], 1)
+    finally:
+        lay.close()
+    log("sparse checkpoints: %.2f of whole-copy bytes, %d boundaries in the bytes of %d; restart level mean %.0f "
+        "vs %.0f, update p50 %.1f vs %.1f ms, mismatches %d; layered %.2f" % (
+            out["stored_over_whole_copy_bytes"], out["ckpts_sparse"], full_ckpts, out["restart_level_mean_sparse"],
+            out["restart_level_mean_full"], out["update_ms_p50_sparse"], out["update_ms_p50_full"],
+            out["mismatches"], out["layered_stored_over_whole_copy_bytes"]))
+    return out
+
+
 def cpu_baseline(Q, W, full_bytes_per_gate, min_s=10.0):
     """The CPU oracle (all host threads, then one) on a bounded sample of the
     headline workload: the 32-qubit circuit's first gates, one at a time,
@@ -815,6 +894,11 @@ def main():
                          "protocols and the 30-qubit fused-unitary legs, printed as one JSON line")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only the serving latency-throughput sweep (several minutes), printed as one JSON line")
+    ap.add_argument("--fusion-only", action="store_true",
+                    help="only the blocked-circuit leg where dense fusion pays, printed as one JSON line")
+    ap.add_argument("--fusion-profile", action="store_true",
+                    help="only the complex64 dense k=5 plan of that leg (b=10, c=4), two full simulations "
+                         "(for counter runs of the matrix-core kernel)")
     ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
     ap.add_argument("--fused-levels", type=int, default=300, help="depth of the fused-unitary leg")
     ap.add_argument("--no-fused-tuned", action="store_true",
@@ -832,6 +916,23 @@ def main():
 
     if args.extras:
         print(json.dumps(run_extras(Q, W, args)))
+        return
+    if args.fusion_only:
+        print(json.dumps(run_fusion_wins(Q, W)))
+        return
+    if args.fusion_profile:
+        nets = W.blocked_circuit(28, 96, 7)
+        s = Q.Simulator(28, "c64", device=0, ckpt_interval=10 ** 6, fusion=Q.QTASK_FUSE_DENSE, fuse_width=5,
+                        tile_bits=10, low_bits=4, autotune=0)
+        try:
+            s.build(nets)
+            runs = [s.update(), s.update(full=True)]
+        finally:
+            s.close()
+        print(json.dumps({"workload": "blocked circuit, 28 qubits, 96 levels, complex64, every stage a dense 5-qubit "
+                                      "unitary on the matrix cores (b=10, c=4)",
+                          "runs": [{"kernel_ms": r["kernel_ms"], "passes": r["passes"], "mfma_flops": r["mfma_flops"]}
+                                   for r in runs]}))
         return
     if args.serving_sweep:
         sweep = {"metric": "serving request latency against offered load", "unit": "ms",
@@ -858,6 +959,7 @@ def main():
     serving = None
     cpu = None
     fusion_wins = None
+    sparse_ckpt = None
     skipped = []
 
     def fits(name, est_s):
@@ -895,6 +997,8 @@ def main():
                        "c128": s128, "c64": s64}
         if fits("fusion_wins", 40):
             fusion_wins = run_fusion_wins(Q, W)
+        if fits("sparse_ckpt", 20):
+            sparse_ckpt = run_sparse_ckpt(Q, W)
         if not args.no_tier24 and fits("tier24", 10 + 1.5 * (args.steps + args.warmup)):
             import numpy as np
             wl = W.config(2)
@@ -955,6 +1059,7 @@ def main():
                      "scope": "every pass launch of the timed steps (32 qubits, complex128)"},
         "tier24": tier24,
         "fusion_wins": fusion_wins,
+        "sparse_ckpt": sparse_ckpt,
         "small_circuit": small,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -259,7 +259,7 @@ __device__ __forceinline__ void op_pc(typename V2<R>::T (&a)[NR], const R *__res
 // complex multiply each) and applied to the registers once, by KOP_PHI.
 template <typename R> struct Pending {
     R r, i;
-    bool hit;
+    uint32_t hit;  // 0 or 1 per lane (a lane value, not a lane mask the op loop would carry in scalars)
 };
 
 template <typename R>
@@ -268,20 +268,20 @@ __device__ __forceinline__ void op_pcl(Pending<R> &ph, const R *__restrict__ c, 
     if (origin_off(sa, base) || origin_off(sb, base)) return;
     if (lane_on(sa, t) && lane_on(sb, t)) {
         cmul_in_place(ph.r, ph.i, c[0], c[1]);
-        ph.hit = true;
+        ph.hit = 1u;
     }
 }
 
 template <typename R>
 __device__ __forceinline__ void op_phi(typename V2<R>::T (&a)[NR], Pending<R> &ph) {
-    if (ph.hit) {
+    if (ph.hit != 0u) {
         const R pr = ph.r, pi = ph.i;
 #pragma unroll
         for (int i = 0; i < NR; ++i) cmul_in_place(a[i].x, a[i].y, pr, pi);
     }
     ph.r = R(1);
     ph.i = R(0);
-    ph.hit = false;
+    ph.hit = 0u;
 }
 
 #define SW1(F)                                   \
@@ -676,7 +676,7 @@ __device__ __forceinline__ void pass_tile(uint32_t idx, const uint32_t *__restri
     // in place across the whole pass.)
     constexpr bool SPLIT = split_lds<R, MF>();
     C a[NR];
-    Pending<R> ph{R(1), R(0), false};
+    Pending<R> ph{R(1), R(0), 0u};
     KOp op = ops[S0->op_begin];
     for (uint32_t si = 0; si < ns; ++si) {
         const KStage *__restrict__ S = S0 + si;

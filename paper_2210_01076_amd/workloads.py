@@ -176,6 +176,20 @@ def blocked_circuit(n: int, levels: int, seed: int, block: int = 5, mix_every: i
     return nets
 
 
+def top_controlled_circuit(n: int, levels: int, seed: int) -> List[Net]:
+    """An H layer, then one gate per level that hinges on the top qubit: a CX
+    or CCX controlled on it, or a CP or CZ with it, the other qubits drawn
+    below.  Each level changes only the amplitudes whose top bit is 1 (half
+    of the blocks), the case sparse checkpoints are for."""
+    rng = np.random.default_rng(seed)
+    nets: List[Net] = [[("h", (q,), ()) for q in range(n)]]
+    for _ in range(levels):
+        kind = ("ccx", "cx", "cp", "cz")[int(rng.integers(4))]
+        rest = [int(q) for q in rng.choice(n - 1, size=2 if kind == "ccx" else 1, replace=False)]
+        nets.append([_gate(rng, kind, [n - 1] + rest)])
+    return nets
+
+
 def ghz_circuit(n: int) -> List[Net]:
     """H on the top qubit, then a CNOT chain from it to every other qubit."""
     top = n - 1
