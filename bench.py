@@ -704,14 +704,20 @@ def run_sparse_ckpt(Q, W, n=24, levels=400, interval=20, full_ckpts=4, edits=20)
         a.build(nets)
         sa = a.update()
         ratio = sa["ckpt_bytes"] / max(sa["ckpt_full_bytes"], 1)
-        b_probe = Q.Simulator(n, "c128", device=0, ckpt_interval=interval, ckpt_delta=1, max_ckpts=1 << 20)
-        try:
-            b_probe.build(nets)
-            sp = b_probe.update()
-            delta_ratio = sp["ckpt_bytes"] / max(sp["ckpt_full_bytes"], 1)
-        finally:
-            b_probe.close()
-        k_delta = max(full_ckpts, int(full_ckpts / max(delta_ratio, 1e-9)))
+        # the most sparse checkpoints that fit in the bytes of the whole copies
+        # (found on plan-only sessions, which lay out the same checkpoints)
+        k_delta, delta_ratio = full_ckpts, 1.0
+        for k in range(4 * full_ckpts, full_ckpts - 1, -1):
+            probe = Q.Simulator(n, "c128", device=Q.QTASK_DEVICE_NONE, ckpt_interval=interval, ckpt_delta=1,
+                                max_ckpts=k)
+            try:
+                probe.build(nets)
+                sp = probe.update()
+            finally:
+                probe.close()
+            if sp["ckpt_bytes"] <= sa["ckpt_bytes"]:
+                k_delta, delta_ratio = k, sp["ckpt_bytes"] / max(sp["ckpt_full_bytes"], 1)
+                break
         b = Q.Simulator(n, "c128", device=0, ckpt_interval=interval, ckpt_delta=1, max_ckpts=k_delta)
         try:
             b.build(nets)
@@ -737,7 +743,7 @@ def run_sparse_ckpt(Q, W, n=24, levels=400, interval=20, full_ckpts=4, edits=20)
             out.update({
                 "ckpt_bytes_full_copies": sa["ckpt_bytes"], "ckpts_full": full_ckpts,
                 "ckpt_bytes_sparse": sb["ckpt_bytes"], "ckpt_full_bytes_sparse_session": sb["ckpt_full_bytes"],
-                "ckpts_sparse": k_delta, "stored_over_whole_copy_bytes": delta_ratio,
+                "ckpts_sparse": k_delta, "stored_over_whole_copy_bytes": sb["ckpt_bytes"] / max(sb["ckpt_full_bytes"], 1),
                 "restart_level_mean_full": sum(r[0] for r in rows) / len(rows),
                 "restart_level_mean_sparse": sum(r[1] for r in rows) / len(rows),
                 "update_ms_p50_full": pct([r[2] for r in rows], 50),
@@ -754,9 +760,10 @@ def run_sparse_ckpt(Q, W, n=24, levels=400, interval=20, full_ckpts=4, edits=20)
         out["layered_stored_over_whole_copy_bytes"] = sl["ckpt_bytes"] / max(sl["ckpt_full_bytes"], 1)
     finally:
         lay.close()
-    log("sparse checkpoints: %.2f of whole-copy bytes, %d boundaries in the bytes of %d; restart level mean %.0f "
-        "vs %.0f, update p50 %.1f vs %.1f ms, mismatches %d; layered %.2f" % (
-            out["stored_over_whole_copy_bytes"], out["ckpts_sparse"], full_ckpts, out["restart_level_mean_sparse"],
+    log("sparse checkpoints: %.2f of whole-copy bytes, %d boundaries in %.2f GB against %d in %.2f GB; restart "
+        "level mean %.0f vs %.0f, update p50 %.1f vs %.1f ms, mismatches %d; layered %.2f" % (
+            out["stored_over_whole_copy_bytes"], out["ckpts_sparse"], out["ckpt_bytes_sparse"] / 1e9, full_ckpts,
+            out["ckpt_bytes_full_copies"] / 1e9, out["restart_level_mean_sparse"],
             out["restart_level_mean_full"], out["update_ms_p50_sparse"], out["update_ms_p50_full"],
             out["mismatches"], out["layered_stored_over_whole_copy_bytes"]))
     return out

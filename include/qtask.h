@@ -114,12 +114,13 @@ typedef struct qtask_opts {
                                sit in the contiguous low positions every tile holds (longer contiguous runs
                                per access at the same number of passes); each segment starts and ends in
                                the plain layout (qubit k at bit k), so checkpoints and queries see it */
-    int32_t ckpt_delta;     /* 1: sparse checkpoints (the paper's copy-on-write blocks, Section III-F): every
-                               segment boundary keeps a checkpoint (max_ckpts is ignored), holding only the blocks
-                               of 2^block_bits amplitudes that the segment before it can change (decided by the
-                               ops' kernel forms); a restore takes each block from the newest checkpoint holding
-                               it.  The affected-block replay (mode 3) is not used with them.  0 (default): whole
-                               copies */
+    int32_t ckpt_delta;     /* 1: sparse checkpoints (the paper's copy-on-write blocks, Section III-F): a
+                               stored boundary's checkpoint holds only the blocks of 2^block_bits amplitudes that
+                               the segments since the previous stored boundary can change (decided by the ops'
+                               kernel forms); a restore takes each block from the newest stored checkpoint holding
+                               it, |0...0> where none does.  max_ckpts thins the stored boundaries as for whole
+                               copies.  The affected-block replay (mode 3) is not used with them.  0 (default):
+                               whole copies */
 } qtask_opts;
 
 typedef struct qtask_s *qtask_t;

@@ -98,7 +98,7 @@ int Session::init_device() {
 // gains or loses a segment keeps its stored boundaries and their checkpoints.
 bool Session::stores_ckpt(size_t j, size_t S) const {
     if (j == 0 || j >= S) return false;
-    if (opts.max_ckpts < 0 || opts.ckpt_delta) return true;
+    if (opts.max_ckpts < 0) return true;
     if (opts.max_ckpts == 0) return false;
     const size_t nb = S - 1;
     size_t stride = std::max<size_t>(ckpt_stride_, 1);
@@ -258,14 +258,38 @@ Session::CkptLayout Session::layout_of(size_t j) const {
     CkptLayout L;
     L.bytes = state_bytes();
     if (!opts.ckpt_delta) return L;
-    const SegmentPlan &sp = *plans_[j - 1];
-    auto it = wsets_.find(sp.hash);
-    if (it == wsets_.end() || it->second.empty()) return L;
+    // the blocks the segments since the previous stored boundary can change
+    const size_t S = segs_.size();
+    size_t i = j - 1;
+    while (i >= 1 && !stores_ckpt(i, S)) --i;
+    uint64_t ukey = 0x554e494f4eull;
+    for (size_t s = i; s < j; ++s) {
+        auto it = wsets_.find(plans_[s]->hash);
+        if (it == wsets_.end() || it->second.empty()) return L;  // a segment that changes every block
+        ukey = hash_mix(ukey, wkeys_.at(plans_[s]->hash));
+    }
+    const std::vector<uint32_t> *blocks = nullptr;
+    if (j - i == 1) {
+        blocks = &wsets_.at(plans_[i]->hash);
+    } else {
+        auto u = unions_.find(ukey);
+        if (u == unions_.end()) {
+            const int beta = std::min(opts.block_bits, n_int);
+            BlockSet w(uint64_t(1) << (n_int - beta));
+            for (size_t s = i; s < j; ++s)
+                for (uint32_t b : wsets_.at(plans_[s]->hash)) w.set(b);
+            u = unions_.emplace(ukey, w.list()).first;
+        }
+        blocks = &u->second;
+        if (blocks->size() == (size_t(1) << (n_int - std::min(opts.block_bits, n_int)))) return L;
+    }
+    uint64_t key = 0x44454c5441ull;
+    for (uint32_t b : *blocks) key = hash_mix(key, b);
     const int beta = std::min(opts.block_bits, n_int);
     L.full = false;
-    L.blocks = &it->second;
-    L.wkey = wkeys_.at(sp.hash);
-    L.bytes = uint64_t(it->second.size()) * (uint64_t(1) << beta) * elem;
+    L.blocks = blocks;
+    L.wkey = key;
+    L.bytes = uint64_t(blocks->size()) * (uint64_t(1) << beta) * elem;
     return L;
 }
 
@@ -633,10 +657,10 @@ int Session::plan_update(bool force_full) {
         };
         for (size_t j = s_edit; j >= 1; --j) {
             if (!usable(j) || segs_[j - 1].hi > L) continue;
-            // a sparse restore reads the checkpoints before it as well
+            // a sparse restore reads the stored checkpoints before it as well
             bool chain = true;
             if (opts.ckpt_delta)
-                for (size_t i = 1; i < j && chain; ++i) chain = usable(i);
+                for (size_t i = 1; i < j && chain; ++i) chain = !stores_ckpt(i, S) || usable(i);
             if (!chain) continue;
             s0 = j;
             break;
@@ -666,6 +690,7 @@ int Session::plan_update(bool force_full) {
                 BlockSet done(nblocks);
                 uint64_t left = nblocks;
                 for (size_t j = s0; j >= 1 && left > 0; --j) {
+                    if (!stores_ckpt(j, S)) continue;
                     const uint64_t a = segs_[j - 1].anchor;
                     const Ckpt &ck = ckpts_.at(a);
                     RestorePart part;

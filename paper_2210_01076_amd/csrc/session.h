@@ -156,6 +156,9 @@ private:
     CkptLayout layout_of(size_t j) const;
     const std::vector<uint32_t> &written_blocks(const SegmentPlan &sp);
     std::unordered_map<uint64_t, std::vector<uint32_t>> wsets_;  // plan hash -> blocks it can change (empty: all)
+    // unions of consecutive segments' block sets (a stored boundary after
+    // boundaries that are not stored), by a key of the segments' set keys
+    mutable std::unordered_map<uint64_t, std::vector<uint32_t>> unions_;
     std::unordered_map<uint64_t, uint64_t> wkeys_;               // plan hash -> key of that list
     int K() const { return opts.ckpt_interval; }
     size_t num_segments() const { return (circ.num_levels() + size_t(K()) - 1) / size_t(K()); }

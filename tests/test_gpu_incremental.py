@@ -264,17 +264,19 @@ def _top_controlled_net(rng, n, kinds=("ccx", "cx", "cp", "cz", "t")):
     return [(kind, tuple([n - 1] + rest), (float(rng.uniform(0, 6)),) if kind == "cp" else ())]
 
 
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_sparse_checkpoints_store_changed_blocks_only(dtype):
+@pytest.mark.parametrize("dtype,max_ckpts", [("c128", -1), ("c64", -1), ("c128", 3)])
+def test_sparse_checkpoints_store_changed_blocks_only(dtype, max_ckpts):
     """Sparse checkpoints on a circuit whose gates all hinge on the top qubit:
-    after the first segment each checkpoint holds the blocks its segment can
-    change (half of them), restarts compose the state from those deltas, and
-    every update equals a full re-simulation bit for bit and the oracle."""
+    after the first segment each checkpoint holds the blocks its segments
+    can change (half of them), restarts compose the state from those deltas,
+    and every update equals a full re-simulation bit for bit and the oracle.
+    With max_ckpts = 3 only some boundaries are stored, each holding the
+    blocks of the segments since the previous stored one."""
     n, bb = 16, 6
     rng = np.random.default_rng(61)
     nets = [[("h", (q,), ()) for q in range(n)]] + [_top_controlled_net(rng, n) for _ in range(40)]
     # complex64 renormalisation rescales every block at each boundary: off here
-    with sim(n, nets, dtype, ckpt_interval=4, block_bits=bb, ckpt_delta=1, renorm=0) as s:
+    with sim(n, nets, dtype, ckpt_interval=4, block_bits=bb, ckpt_delta=1, renorm=0, max_ckpts=max_ckpts) as s:
         s.update()
         st = s.stats()
         assert 0 < st["ckpt_bytes"] < st["ckpt_full_bytes"]

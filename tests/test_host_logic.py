@@ -808,23 +808,29 @@ def _sparse_net(rng, n):
     return [(kind, tuple([n - 1] + rest), (float(rng.uniform(0, 6)),) if kind == "cp" else ())]
 
 
-@pytest.mark.parametrize("seed", range(4))
-def test_sparse_checkpoints_hold_every_changed_block(seed):
-    """With sparse checkpoints on, each boundary's checkpoint lists the
-    blocks the segment before it can change; the blocks that actually change
-    between consecutive boundaries (oracle snapshots) lie among them, and
-    the checkpoints hold fewer bytes than whole copies."""
+@pytest.mark.parametrize("seed,max_ckpts", [(0, -1), (1, -1), (2, 2), (3, 3)])
+def test_sparse_checkpoints_hold_every_changed_block(seed, max_ckpts):
+    """With sparse checkpoints on, each stored boundary's checkpoint lists
+    the blocks the segments since the previous stored boundary can change;
+    the blocks that actually change between consecutive stored boundaries
+    (oracle snapshots) lie among them, and the checkpoints hold fewer bytes
+    than whole copies.  With max_ckpts the stored boundaries thin out and
+    each checkpoint covers several segments."""
     rng = np.random.default_rng(40 + seed)
     n, bb, K = 9, 3, 3
     prep = [[("h", (q,), ()) for q in range(n)]]
-    nets = prep + [_sparse_net(rng, n) for _ in range(14)]
-    with plan_only(n, block_bits=bb, ckpt_interval=K, tile_bits=6, low_bits=2, ckpt_delta=1) as sim:
+    nets = prep + [_sparse_net(rng, n) for _ in range(20)]
+    with plan_only(n, block_bits=bb, ckpt_interval=K, tile_bits=6, low_bits=2, ckpt_delta=1,
+                   max_ckpts=max_ckpts) as sim:
         sim.build(nets)
         st = sim.update()
         dump = sim.dump()
     snaps = oracle.snapshots(n, nets)
     cks = dump["checkpoints"]
-    assert len(cks) == len(dump["segments"]) - 1
+    if max_ckpts < 0:
+        assert len(cks) == len(dump["segments"]) - 1
+    else:
+        assert 0 < len(cks) <= max_ckpts
     sparse = 0
     prev = 0
     for ck in cks:
