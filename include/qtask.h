@@ -337,6 +337,12 @@ int qtask_server_usage(qtask_server_t s, uint64_t *bytes, int32_t *resident);
 /* Largest value the admitted bytes reached since the server was created
  * (never above budget_bytes). */
 int qtask_server_peak_bytes(qtask_server_t s, uint64_t *peak);
+/* Where the server's requests ran, since it was created: *batched counts
+ * requests started in batched ticks (small sessions, any pass kernel
+ * variant), *streamed requests launched on their session's own stream
+ * (large sessions, and plans with sparse-checkpoint block copies), *ticks
+ * the batched ticks. */
+int qtask_server_paths(qtask_server_t s, uint64_t *batched, uint64_t *streamed, uint64_t *ticks);
 
 #ifdef __cplusplus
 }

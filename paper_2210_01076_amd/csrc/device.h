@@ -10,10 +10,27 @@ namespace qtask {
 // One pass over `n_tiles` tiles of 2^b amplitudes (dtype 0: complex128, 1: complex64).
 hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s);
 
+// Whether a pass runs in the matrix-core variant of the pass kernel: it has
+// matrix-core stages, or dense stages in complex128 (the complex128
+// vector-ALU variant exchanges real and imaginary parts in turn and leaves
+// dense stages out).  That variant exchanges whole complex values through
+// LDS: 2^b x sizeof(complex) bytes per tile.
+inline bool pass_uses_mf(int dtype, const KArgs &a) { return a.has_mfma || (dtype == 0 && a.has_dense); }
+
+// LDS bytes per tile of 2^b amplitudes for a pass kernel variant.
+inline uint32_t pass_lds_bytes(int dtype, bool mf, int b) {
+    const uint32_t part = dtype == 0 ? 8u : 4u;
+    return (1u << b) * (dtype == 0 && !mf ? part : 2u * part);
+}
+
 // Batched small-session pass round: the item count is read from `count`
 // (device memory); `n_groups` workgroups of `threads` threads and
-// `lds_bytes` LDS each (items must all use that thread count).
-hipError_t launch_pass_batch(int dtype, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,
+// `lds_bytes` LDS each (items must all use that thread count).  With `mf`
+// set, each item runs in the variant pass_uses_mf picks for it (so the
+// result is the one launch_pass gives), and lds_bytes must be
+// pass_lds_bytes(dtype, true, b); without it every item must be a pass
+// for which pass_uses_mf is false.
+hipError_t launch_pass_batch(int dtype, bool mf, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,
                              uint32_t threads, uint32_t lds_bytes, hipStream_t s);
 // Batched renormalisation sums (one workgroup per item, count in device memory).
 hipError_t launch_batch_sums(const KSumItem *items, const uint32_t *count, uint32_t n_groups, hipStream_t s);

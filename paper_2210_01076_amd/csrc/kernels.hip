@@ -844,7 +844,11 @@ qk_pass<double, false>(void *dst, const void *src, void *ckpt, const KPass *__re
 // finds its item by binary search over the items' first workgroup index;
 // every decision below depends only on blockIdx and the table, so a
 // workgroup either runs the whole pass body or leaves before any barrier.
-template <typename R>
+// The MF instantiation holds both pass bodies and runs, per item, the one
+// the single-session launcher would pick (matrix-core stages, or dense
+// stages in complex128, take the matrix-core body), so a session's result
+// does not depend on which sessions share its round.
+template <typename R, bool MF>
 __global__ void __launch_bounds__(512)
 qk_pass_batch(const KBatchItem *__restrict__ items, const uint32_t *__restrict__ count) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -861,6 +865,14 @@ qk_pass_batch(const KBatchItem *__restrict__ items, const uint32_t *__restrict__
     const uint32_t local = blockIdx.x - it->tile_begin;
     if (local >= it->n_tiles || it->threads != blockDim.x) return;
     const KArgs &a = it->args;
+    if constexpr (MF) {
+        if (a.has_mfma || (sizeof(R) == 8 && a.has_dense)) {
+            pass_tile<R, true>(local, a.tile_list, a.dst, a.src, a.ckpt, a.pass, a.stages, a.ops,
+                               static_cast<const R *>(a.coefs), a.store_mask, a.scale, a.partials, a.src_basis,
+                               a.block_bits, reinterpret_cast<C *>(smem));
+            return;
+        }
+    }
     pass_tile<R, false>(local, a.tile_list, a.dst, a.src, a.ckpt, a.pass, a.stages,
                          a.ops, static_cast<const R *>(a.coefs), a.store_mask, a.scale, a.partials, a.src_basis,
                          a.block_bits, reinterpret_cast<C *>(smem));
@@ -1096,8 +1108,9 @@ uint32_t fill_grid(uint64_t n) {
 
 template <typename R, bool MF>
 hipError_t launch_pass_t(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
+    static_assert(split_lds<R, MF>() == (sizeof(R) == 8 && !MF), "pass_lds_bytes assumes this exchange rule");
     const uint32_t threads = 1u << (b - QK_G);
-    const size_t lds = (size_t(1) << b) * (split_lds<R, MF>() ? sizeof(R) : sizeof(typename V2<R>::T));
+    const size_t lds = pass_lds_bytes(sizeof(R) == 8 ? 0 : 1, MF, b);
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass<R, MF>), lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((qk_pass<R, MF>), dim3(n_tiles), dim3(threads), lds, s, a.dst, a.src, a.ckpt, a.pass,
@@ -1109,24 +1122,28 @@ hipError_t launch_pass_t(const KArgs &a, uint32_t n_tiles, int b, hipStream_t s)
 hipError_t launch_pass(int dtype, const KArgs &a, uint32_t n_tiles, int b, hipStream_t s) {
     (void)hipGetLastError();  // start from a clean error state
     if (n_tiles == 0) return hipSuccess;
-    if (a.has_mfma || (dtype == 0 && a.has_dense))
+    if (pass_uses_mf(dtype, a))
         return dtype == 0 ? launch_pass_t<double, true>(a, n_tiles, b, s) : launch_pass_t<float, true>(a, n_tiles, b, s);
     return dtype == 0 ? launch_pass_t<double, false>(a, n_tiles, b, s) : launch_pass_t<float, false>(a, n_tiles, b, s);
 }
 
-hipError_t launch_pass_batch(int dtype, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,
+template <typename R, bool MF>
+hipError_t launch_pass_batch_t(const KBatchItem *items, const uint32_t *count, uint32_t n_groups, uint32_t threads,
+                               uint32_t lds_bytes, hipStream_t s) {
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<R, MF>), lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((qk_pass_batch<R, MF>), dim3(n_groups), dim3(threads), lds_bytes, s, items, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_batch(int dtype, bool mf, const KBatchItem *items, const uint32_t *count, uint32_t n_groups,
                              uint32_t threads, uint32_t lds_bytes, hipStream_t s) {
     (void)hipGetLastError();
-    if (dtype == 0) {
-        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<double>), lds_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(qk_pass_batch<double>, dim3(n_groups), dim3(threads), lds_bytes, s, items, count);
-    } else {
-        hipError_t e = allow_lds(reinterpret_cast<const void *>(&qk_pass_batch<float>), lds_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(qk_pass_batch<float>, dim3(n_groups), dim3(threads), lds_bytes, s, items, count);
-    }
-    return hipGetLastError();
+    if (dtype == 0)
+        return mf ? launch_pass_batch_t<double, true>(items, count, n_groups, threads, lds_bytes, s)
+                  : launch_pass_batch_t<double, false>(items, count, n_groups, threads, lds_bytes, s);
+    return mf ? launch_pass_batch_t<float, true>(items, count, n_groups, threads, lds_bytes, s)
+              : launch_pass_batch_t<float, false>(items, count, n_groups, threads, lds_bytes, s);
 }
 
 hipError_t launch_batch_sums(const KSumItem *items, const uint32_t *count, uint32_t n_groups, hipStream_t s) {

@@ -24,6 +24,7 @@
 //  - Waiting requests start oldest first, or (order 1) expected-shortest
 //    first, the estimate 2^n x levels divided by 1 + waiting time / 1 s.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -81,9 +82,9 @@ struct SSession {
 };
 
 struct GraphKey {
-    int dtype, threads, rounds, groups;
+    int dtype, mf, threads, rounds, groups;
     bool operator<(const GraphKey &o) const {
-        return std::tie(dtype, threads, rounds, groups) < std::tie(o.dtype, o.threads, o.rounds, o.groups);
+        return std::tie(dtype, mf, threads, rounds, groups) < std::tie(o.dtype, o.mf, o.threads, o.rounds, o.groups);
     }
 };
 
@@ -121,12 +122,13 @@ struct qtask_server_s {
     std::vector<int32_t> tick_sessions;
     BatchTables tables;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    std::atomic<uint64_t> n_batched{0}, n_streamed{0}, n_ticks{0};
     std::string error;
 
     double clock() const { return now_ms() - t0; }
     void run();
     int start_small_tick(std::vector<int32_t> &ready, std::vector<int32_t> &group);
-    int launch_rounds(int dtype, uint32_t threads, uint32_t lds, uint32_t rounds, uint32_t groups);
+    int launch_rounds(int dtype, bool mf, uint32_t threads, uint32_t lds, uint32_t rounds, uint32_t groups);
     void finish(int32_t sid, double done_ms);
     int admit(int32_t sid, uint64_t need);
     void evict(int32_t victim);
@@ -265,12 +267,13 @@ void qtask_server_s::finish(int32_t sid, double done_ms) {
     cv_done.notify_all();
 }
 
-int qtask_server_s::launch_rounds(int dtype, uint32_t threads, uint32_t lds, uint32_t rounds, uint32_t groups) {
+int qtask_server_s::launch_rounds(int dtype, bool mf, uint32_t threads, uint32_t lds, uint32_t rounds,
+                                  uint32_t groups) {
     // rounds and groups are capacities: the tables say how much work each round has
-    const GraphKey key{dtype, int(threads), int(rounds), int(groups)};
+    const GraphKey key{dtype, int(mf), int(threads), int(rounds), int(groups)};
     auto enqueue = [&]() -> int {
         for (uint32_t r = 0; r < rounds; ++r) {
-            if (qtask::launch_pass_batch(dtype, tables.d_items + size_t(r) * kMaxItems, tables.d_counts + r, groups,
+            if (qtask::launch_pass_batch(dtype, mf, tables.d_items + size_t(r) * kMaxItems, tables.d_counts + r, groups,
                                          threads, lds, bstream) != hipSuccess)
                 return QTASK_E_DEVICE;
             if (qtask::launch_batch_sums(tables.d_sums + size_t(r) * kMaxItems, tables.d_counts + tables.rounds + r,
@@ -321,9 +324,12 @@ int qtask_server_s::start_small_tick(std::vector<int32_t> &ready, std::vector<in
     ready.swap(rest);
     if (b < 0) b = QK_MIN_TILE_BITS;  // no pass work in this tick
     const uint32_t threads = 1u << (b - QK_G);
-    // 8 bytes per amplitude: a complex64 value, or one part of a complex128
-    // value (the complex128 kernel exchanges real and imaginary parts in turn)
-    const uint32_t lds = (1u << b) * 8u;
+    // the matrix-core kernel variant when any pass of the tick needs it (it
+    // runs the other passes in the vector-ALU body, as their own launch would)
+    bool mf = false;
+    for (int32_t sid : group)
+        for (const auto &l : sess[sid].s->launches) mf = mf || (l.n_tiles > 0 && qtask::pass_uses_mf(dtype, l.args));
+    const uint32_t lds = qtask::pass_lds_bytes(dtype, mf, b);
     size_t max_rounds = 0;
     uint32_t max_groups = 1;
     for (int32_t sid : group) {
@@ -391,7 +397,7 @@ int qtask_server_s::start_small_tick(std::vector<int32_t> &ready, std::vector<in
             hipMemcpyAsync(tables.d_counts, tables.h_counts, sizeof(uint32_t) * 2 * tr, hipMemcpyHostToDevice,
                            bstream) != hipSuccess)
             return QTASK_E_DEVICE;
-        int rc = launch_rounds(dtype, threads, lds, rcap, gcap);
+        int rc = launch_rounds(dtype, mf, threads, lds, rcap, gcap);
         if (rc != QTASK_OK) return rc;
         // the staging buffers are reused by the next chunk: wait for the copies
         if (r0 + rcap < max_rounds && hipStreamSynchronize(bstream) != hipSuccess) return QTASK_E_DEVICE;
@@ -403,6 +409,8 @@ int qtask_server_s::start_small_tick(std::vector<int32_t> &ready, std::vector<in
     if (hipEventRecord(bdone, bstream) != hipSuccess) return QTASK_E_DEVICE;
     tick_sessions = group;
     tick_inflight = true;
+    n_ticks += 1;
+    n_batched += group.size();
     return QTASK_OK;
 }
 
@@ -549,11 +557,11 @@ void qtask_server_s::run() {
                 fail(sid, rc, rc != QTASK_E_DEVICE);
                 continue;
             }
-            // the batched kernel runs pass launches without matrix-core
-            // stages: other plans (and sparse-checkpoint copies) run on the
+            // the batched kernel runs pass launches of every kernel variant;
+            // plans with block copies (sparse checkpoints) run on the
             // session's own stream
             bool own = ss.s->opts.ckpt_delta != 0;
-            for (const auto &l : ss.s->launches) own = own || l.args.has_mfma || l.args.has_dense || l.kind != 0;
+            for (const auto &l : ss.s->launches) own = own || l.kind != 0;
             ss.batched = ss.small && !own;
             if (ss.batched) {
                 // plan uploads went to the session's stream
@@ -568,6 +576,8 @@ void qtask_server_s::run() {
                 (void)hipStreamSynchronize(ss.s->stream);
                 ss.s->invalidate();
                 fail(sid, QTASK_E_DEVICE, false);
+            } else {
+                n_streamed += 1;
             }
         }
         // 3. a batched tick when none is running; sessions that become ready
@@ -802,6 +812,14 @@ int qtask_server_usage(qtask_server_t sv, uint64_t *bytes, int32_t *resident) {
     std::lock_guard<std::mutex> lk(sv->mu);
     *bytes = sv->used;
     *resident = sv->resident;
+    return QTASK_OK;
+}
+
+int qtask_server_paths(qtask_server_t sv, uint64_t *batched, uint64_t *streamed, uint64_t *ticks) {
+    if (!sv || !batched || !streamed || !ticks) return QTASK_E_ARG;
+    *batched = sv->n_batched.load();
+    *streamed = sv->n_streamed.load();
+    *ticks = sv->n_ticks.load();
     return QTASK_OK;
 }
 

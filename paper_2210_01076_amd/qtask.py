@@ -117,6 +117,7 @@ _SIGS = {
     "qtask_server_session": ([vp, i32, P(vp)], ctypes.c_int),
     "qtask_server_usage": ([vp, P(u64), P(i32)], ctypes.c_int),
     "qtask_server_peak_bytes": ([vp, P(u64)], ctypes.c_int),
+    "qtask_server_paths": ([vp, P(u64), P(u64), P(u64)], ctypes.c_int),
 }
 
 _lib = None
@@ -402,6 +403,14 @@ def qtask_server_peak_bytes(s) -> int:
     b = u64()
     check(load().qtask_server_peak_bytes(s, ctypes.byref(b)), "qtask_server_peak_bytes")
     return b.value
+
+
+def qtask_server_paths(s) -> dict:
+    """Requests started in batched ticks, requests launched on their
+    session's own stream, and batched ticks, since the server was created."""
+    a, b, t = u64(), u64(), u64()
+    check(load().qtask_server_paths(s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)), "qtask_server_paths")
+    return {"batched": a.value, "streamed": b.value, "ticks": t.value}
 
 
 # ------------------------------------------------------------- convenience

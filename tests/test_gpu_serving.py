@@ -48,9 +48,10 @@ def _serve(specs, opts, phases, read_states=True, **sopts):
     sv = Q.qtask_server_create(Q.qtask_server_opts_default(**sopts))
     try:
         sids, tickets = [], {}
-        for n, dtype, nets, _ in specs:
+        for i, (n, dtype, nets, _) in enumerate(specs):
             dt = Q.QTASK_C128 if dtype == "c128" else Q.QTASK_C64
-            sids.append(Q.qtask_server_open(sv, n, dt, Q.qtask_opts_default(device=0, **opts), nets))
+            o = opts[i] if isinstance(opts, list) else opts
+            sids.append(Q.qtask_server_open(sv, n, dt, Q.qtask_opts_default(device=0, **o), nets))
         for i, sid in enumerate(sids):
             tickets[(i, 0)] = Q.qtask_server_submit(sv, sid, [])
         usage = []
@@ -61,6 +62,7 @@ def _serve(specs, opts, phases, read_states=True, **sopts):
             Q.qtask_server_drain(sv)
             usage.append(Q.qtask_server_usage(sv))
         results = {k: Q.qtask_server_wait(sv, t, 0.0) for k, t in tickets.items()}
+        _serve.paths = Q.qtask_server_paths(sv)
         states = []
         if read_states:
             for i, sid in enumerate(sids):
@@ -83,6 +85,7 @@ def test_small_sessions_alone_equals_mix(use_graph):
     opts = dict(ckpt_interval=5)
     alone = [_alone(n, d, nets, reqs, opts) for n, d, nets, reqs in specs]
     results, states, usage = _serve(specs, opts, [_interleaved(specs, 3)], use_graph=use_graph)
+    assert _serve.paths["streamed"] == 0 and _serve.paths["batched"] == len(results), _serve.paths
     for (i, r), res in sorted(results.items()):
         assert res["status"] == Q.QTASK_OK, (i, r, res["status"])
         assert res["state_hash"] == alone[i][0][r], "session %d request %d differs from its run alone" % (i, r)
@@ -91,6 +94,35 @@ def test_small_sessions_alone_equals_mix(use_graph):
         assert bytes_equal(states[i], alone[i][1])
         check_state(states[i], oracle.simulate(n, alone[i][2]), d, "session %d" % i)
     log("small mix ok, usage", usage)
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_fused_small_sessions_stay_batched(use_graph):
+    """Small sessions whose plans have dense fused stages (on the matrix
+    cores at 10 qubits and up, on the vector ALU below) share batched ticks
+    with unfused ones: the batched kernel runs each pass in the variant the
+    session's own launch would use, so every result equals the run alone
+    and no request leaves the batched path."""
+    specs = _specs(53, 12, 6, 15, 12, 3)
+    opts = []
+    for i, (n, _, _, _) in enumerate(specs):
+        if i % 3 == 2:
+            opts.append(dict(ckpt_interval=5))
+        elif n >= 10:
+            opts.append(dict(ckpt_interval=5, fusion=Q.QTASK_FUSE_DENSE, fuse_width=5, tile_bits=10))
+        else:
+            opts.append(dict(ckpt_interval=5, fusion=Q.QTASK_FUSE_DENSE, fuse_width=4))
+    alone = [_alone(n, d, nets, reqs, opts[i]) for i, (n, d, nets, reqs) in enumerate(specs)]
+    results, states, _ = _serve(specs, opts, [_interleaved(specs, 3)], use_graph=use_graph)
+    paths = _serve.paths
+    assert paths["streamed"] == 0 and paths["batched"] == len(results), paths
+    for (i, r), res in sorted(results.items()):
+        assert res["status"] == Q.QTASK_OK, (i, r, res["status"])
+        assert res["state_hash"] == alone[i][0][r], "session %d request %d differs from its run alone" % (i, r)
+    for i, (n, d, _, _) in enumerate(specs):
+        assert bytes_equal(states[i], alone[i][1])
+        check_state(states[i], oracle.simulate(n, alone[i][2]), d, "session %d" % i)
+    log("fused small mix ok, paths", paths)
 
 
 @pytest.mark.parametrize("order", [0, 1])
