@@ -105,7 +105,9 @@ typedef struct qtask_opts {
                                and fuse_width.  The pick is cached per process and frozen for the session */
     int32_t closed_mode;    /* 1 (default): replay only affected blocks when the affected set is closed */
     void *stream;           /* hipStream_t for all work; NULL = a library-owned stream */
-    void *(*alloc)(size_t bytes, void *ctx); /* device allocator; NULL = hipMalloc */
+    void *(*alloc)(size_t bytes, void *ctx); /* device allocator; NULL = hipMalloc.  Must return memory aligned to
+                                                 256 bytes (as hipMalloc does); other memory is freed and the
+                                                 allocation fails */
     void (*free)(void *ptr, void *ctx);
     void *alloc_ctx;
     int32_t relabel;        /* qubit relabelling inside checkpoint segments: 1 on, 0 off, -1 (default) on for

@@ -78,7 +78,7 @@ struct KStage {
     uint64_t g_bit[QK_G];             // first/last stage: global offset of register-index bit j
     uint64_t g_thr[QK_MAX_THR_BITS];  // first/last stage: global offset of thread-index bit k
     uint32_t k;                       // MFMA stage: qubits of the dense unitary
-    uint32_t coef;                    // MFMA stage: offset of the 2^k x 2^k matrix (interleaved)
+    uint32_t coef;                    // MFMA stage: offset of the real block operand in lane order (16-value aligned)
     uint32_t n_col_bits;              // MFMA stage: b - k
     uint32_t row_off[1 << QK_MAX_DENSE_K]; // MFMA stage: LDS slot of row r (the k stage bits)
     uint32_t col_off[QK_MAX_TILE_BITS];    // MFMA stage: LDS slot contribution of column bit

@@ -504,15 +504,18 @@ template <> struct MfmaT<float> {
     static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
-// Element of the real block matrix [[Ur, -Ui], [Ui, Ur]] at real row rr and
-// real column kk.  Whether it is a real or an imaginary part, and its sign,
-// depend only on the halves rr and kk fall in.
-template <typename R, int DIM>
-__device__ __forceinline__ R block_elem(const R *__restrict__ U, int rr, int kk) {
-    const int ur = rr & (DIM - 1), uk = kk & (DIM - 1);
-    const bool top = rr < DIM, right = kk >= DIM;
-    const R v = U[2 * (ur * DIM + uk) + (top == right ? 1 : 0)];
-    return (top && right) ? -v : v;
+// N consecutive values from p with vector loads of up to 16 bytes (p is
+// aligned to the load size).
+template <typename R, int N>
+__device__ __forceinline__ void load_vec(const R *__restrict__ p, R (&v)[N]) {
+    constexpr int W = N * int(sizeof(R)) >= 16 ? 16 / int(sizeof(R)) : N;
+    typedef R vt __attribute__((ext_vector_type(W)));
+#pragma unroll
+    for (int c = 0; c < N / W; ++c) {
+        const vt w = reinterpret_cast<const vt *>(p)[c];
+#pragma unroll
+        for (int j = 0; j < W; ++j) v[c * W + j] = w[j];
+    }
 }
 
 template <typename R, int K>
@@ -528,7 +531,10 @@ __device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const
     // bytes per lane (64 VGPRs at K = 5 in FP32, 32 at K = 4 in FP64)
     constexpr bool A_REG = sizeof(R) == 4 ? K <= 5 : K <= 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const R *__restrict__ U = coefs + S->coef;
+    // the planner stores the block operand in lane order: this lane's RB
+    // values of step s (rows 16 rb + lane % 16, column 4 s + lane / 16) are
+    // contiguous at (s * 64 + lane) * RB
+    const R *__restrict__ A = coefs + S->coef + lane * RB;
     // LDS slot contributions (the slot map is linear over the bits of the
     // row and column indices): unrolled branch-free selects over the tables,
     // whose unused entries are zero
@@ -553,19 +559,17 @@ __device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const
         for (int j = 0; j < K; ++j) o ^= rbit[j] & (0u - ((uint32_t(r) >> j) & 1u));
         return o;
     };
-    R areg[A_REG ? KS : 1][A_REG ? RB : 1];
+    R areg[A_REG ? KS : 1][RB];
     if constexpr (A_REG) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) areg[s][rb] = block_elem<R, DIM>(U, 16 * rb + (lane & 15), 4 * s + (lane >> 4));
+        for (int s = 0; s < KS; ++s) load_vec<R, RB>(A + s * 64 * RB, areg[s]);
     }
     typename M::acc_t acc[RB][CB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = typename M::acc_t{0, 0, 0, 0};
-    auto step = [&](int s, auto a_of) {
+    auto step = [&](int s, const R (&av)[RB]) {
         const int kk = 4 * s + (lane >> 4);          // real inner index of this lane
         const uint32_t roff = row_slot(kk & (DIM - 1));
         const int part = kk >= DIM ? 1 : 0;          // 0: Xr, 1: Xi
@@ -573,19 +577,20 @@ __device__ __forceinline__ void mfma_stage_k(const KStage *__restrict__ S, const
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) bv[cb] = lr[2 * (cb_off[cb] ^ roff) + part];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const R av = a_of(s, rb, kk);
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = M::mma(av, bv[cb], acc[rb][cb]);
-        }
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = M::mma(av[rb], bv[cb], acc[rb][cb]);
     };
     if constexpr (A_REG) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) step(s, [&](int s_, int rb, int) { return areg[s_][rb]; });
+        for (int s = 0; s < KS; ++s) step(s, areg[s]);
     } else {
 #pragma unroll 4
-        for (int s = 0; s < KS; ++s)
-            step(s, [&](int, int rb, int kk) { return block_elem<R, DIM>(U, 16 * rb + (lane & 15), kk); });
+        for (int s = 0; s < KS; ++s) {
+            R av[RB];
+            load_vec<R, RB>(A + s * 64 * RB, av);
+            step(s, av);
+        }
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)

@@ -700,6 +700,32 @@ struct Packer {
     }
 };
 
+// A matrix-core stage's operand in the order the kernel's lanes read it.
+// The stage multiplies by the real block matrix M = [[Ur, -Ui], [Ui, Ur]]
+// (2^(k+1) rows and columns) with 16x16x4 matrix instructions: in inner
+// step s, lane l of a wave holds, for row block rb, the element of M at row
+// 16 rb + l % 16 and column 4 s + l / 16.  That element is stored at
+// (s * 64 + l) * RB + rb (RB = 2^(k+1) / 16 row blocks), so each lane reads
+// the RB values of a step as one contiguous vector.  Values are rounded
+// once from the FP64 unitary.  Returns the count written (4 * 4^k).
+constexpr size_t kMfmaAlign = 16;  // operand offset alignment, in values
+
+template <typename R>
+size_t pack_mfma_operand(const std::vector<cd> &U, int k, R *out) {
+    const int dim = 1 << k, mr = 2 * dim, rb_n = mr / 16, steps = mr / 4;
+    for (int s = 0; s < steps; ++s)
+        for (int l = 0; l < 64; ++l)
+            for (int rb = 0; rb < rb_n; ++rb) {
+                const int row = 16 * rb + (l & 15), col = 4 * s + (l >> 4);
+                const cd z = U[size_t(row & (dim - 1)) * dim + (col & (dim - 1))];
+                const bool top = row < dim, right = col >= dim;
+                double v = top == right ? z.imag() : z.real();  // Ui in the off-diagonal blocks
+                if (top && right) v = -v;
+                out[size_t(s * 64 + l) * rb_n + rb] = R(v);
+            }
+    return size_t(mr) * mr;
+}
+
 template <typename R>
 void pack_blob(SegmentPlan &sp) {
     const PlanParams &pp = sp.pp;
@@ -709,7 +735,7 @@ void pack_blob(SegmentPlan &sp) {
     for (const auto &ps : sp.passes)
         for (const auto &st : ps.stages) {
             ++n_stage;
-            if (st.mfma) n_coef += st.U.size() * 2;
+            if (st.mfma) n_coef += kMfmaAlign + 2 * st.U.size() * 2;  // block form, aligned
             else if (!st.U.empty()) { n_op += 1; n_coef += st.U.size() * 2; }
             else {
                 for (const auto &g : st.ops) { ++n_op; n_coef += g.coef.size(); }
@@ -775,8 +801,9 @@ void pack_blob(SegmentPlan &sp) {
                     S.row_off[r] = o;
                 }
                 for (int j = 0; j < b - W; ++j) S.col_off[j] = phys(st.tpos[j]);
+                ci = (ci + kMfmaAlign - 1) / kMfmaAlign * kMfmaAlign;
                 S.coef = uint32_t(ci);
-                for (const cd &z : st.U) { kc[ci++] = R(z.real()); kc[ci++] = R(z.imag()); }
+                ci += pack_mfma_operand(st.U, W, kc + ci);
                 S.op_begin = uint32_t(oi);
                 S.op_count = 0;
                 continue;

@@ -63,7 +63,16 @@ Session::~Session() {
 
 void *Session::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 256;
-    if (opts.alloc) return opts.alloc(bytes, opts.alloc_ctx);
+    if (opts.alloc) {
+        // the kernels read plan records and operands with aligned vector loads
+        void *p = opts.alloc(bytes, opts.alloc_ctx);
+        if (p && (reinterpret_cast<uintptr_t>(p) & 255u) != 0) {
+            if (opts.free) opts.free(p, opts.alloc_ctx);
+            last_error = "alloc hook returned memory not aligned to 256 bytes";
+            return nullptr;
+        }
+        return p;
+    }
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();

@@ -712,6 +712,29 @@ def _apply_kop(a, op, coefs, t=None, base=0, ph=None):
         raise AssertionError("op type %d" % ty)
 
 
+def _mfma_operand(coefs, off, k):
+    """The complex unitary of a matrix-core stage, decoded from its operand:
+    the real block matrix M = [[Ur, -Ui], [Ui, Ur]] in the order the 16x16x4
+    matrix instructions read it (in inner step s, lane l holds row
+    16 rb + l % 16, column 4 s + l // 16 of M for each row block rb, stored
+    at (s * 64 + l) * RB + rb).  Checks the block structure on the way."""
+    dim = 1 << k
+    mr = 2 * dim
+    rbn, steps = mr // 16, mr // 4
+    assert off % 16 == 0, "operand offset must allow aligned vector loads"
+    blk = np.asarray(coefs[off:off + mr * mr], dtype=np.float64)
+    assert blk.size == mr * mr
+    M = np.full((mr, mr), np.nan)
+    lane = np.arange(64)
+    for s_ in range(steps):
+        for rb in range(rbn):
+            M[16 * rb + (lane & 15), 4 * s_ + (lane >> 4)] = blk[(s_ * 64 + lane) * rbn + rb]
+    assert not np.isnan(M).any()
+    Ur, Ui = M[:dim, :dim], M[dim:, :dim]
+    assert np.array_equal(M[dim:, dim:], Ur) and np.array_equal(M[:dim, dim:], -Ui)
+    return Ur + 1j * Ui
+
+
 def emulate_kernel(dump, n):
     """Run the plan blobs the way the pass kernel does, tile by tile: the
     tile origin from the deposit runs, the first stage's registers loaded
@@ -741,10 +764,7 @@ def emulate_kernel(dump, n):
                 ph = {"f": np.ones(nthr, dtype=np.complex128), "hit": np.zeros(nthr, dtype=bool)}
                 for si, S in enumerate(stages):
                     if S["kind"] == 1:  # dense unitary on LDS
-                        k = S["k"]
-                        dim = 1 << k
-                        U = coefs[S["coef"]:S["coef"] + 2 * dim * dim]
-                        U = (U[0::2] + 1j * U[1::2]).reshape(dim, dim)
+                        U = _mfma_operand(coefs, S["coef"], S["k"])
                         cols = _xor_bits(S["col_off"], np.arange(1 << len(S["col_off"]), dtype=np.int64),
                                          len(S["col_off"]))
                         slots = np.array(S["row_off"], dtype=np.int64)[:, None] ^ cols[None, :]
