@@ -169,6 +169,7 @@ def run_serving(Q, W, dtype, specs, keep_n=20, order=0):
         lat = [r["latency_ms"] for r in res]
         svc = [r["done_ms"] - r["start_ms"] for r in res]
         used, resident = Q.qtask_server_usage(sv)
+        paths = Q.qtask_server_paths(sv)
         kept = {}
         for i, sid in enumerate(sids):
             if specs[i].n <= keep_n:
@@ -191,6 +192,8 @@ def run_serving(Q, W, dtype, specs, keep_n=20, order=0):
             "initial_sim_s": warm_s,
             "device_bytes": used,
             "resident": resident,
+            "batched_requests": paths["batched"],
+            "stream_requests": paths["streamed"],
         }
         return out, kept
     finally:
@@ -262,6 +265,7 @@ def run_serving_curve(Q, W, dtype, rates, per_phase=128, keep_n=20, seed=4242):
             curve.append(point)
         used, resident = Q.qtask_server_usage(sv)
         peak = Q.qtask_server_peak_bytes(sv)
+        paths = Q.qtask_server_paths(sv)
         kept = {}
         for i, sid in enumerate(sids):
             if specs[i].n <= keep_n:
@@ -275,7 +279,8 @@ def run_serving_curve(Q, W, dtype, rates, per_phase=128, keep_n=20, seed=4242):
         return {"dtype": dtype, "sessions": len(sids), "failed": bad, "curve": curve,
                 "updates_per_s": sat["served_per_s"], "latency_ms_p50": sat["latency_ms_p50"],
                 "latency_ms_p99": sat["latency_ms_p99"], "budget_bytes": budget, "peak_bytes": peak,
-                "device_bytes": used, "resident": resident}, kept
+                "device_bytes": used, "resident": resident, "batched_requests": paths["batched"],
+                "stream_requests": paths["streamed"], "batched_ticks": paths["ticks"]}, kept
     finally:
         Q.qtask_server_destroy(sv)
 
@@ -903,9 +908,9 @@ def main():
                     help="only the serving latency-throughput sweep (several minutes), printed as one JSON line")
     ap.add_argument("--fusion-only", action="store_true",
                     help="only the blocked-circuit leg where dense fusion pays, printed as one JSON line")
-    ap.add_argument("--fusion-profile", action="store_true",
-                    help="only the complex64 dense k=5 plan of that leg (b=10, c=4), two full simulations "
-                         "(for counter runs of the matrix-core kernel)")
+    ap.add_argument("--fusion-profile", nargs="?", const="c64:10", default=None, metavar="DTYPE:B",
+                    help="only the dense k=5 plan of that leg in one dtype and tile size (default c64:10, c=4), "
+                         "two full simulations (for counter runs of the matrix-core kernel)")
     ap.add_argument("--fused-qubits", type=int, default=30, help="state size of the fused-unitary leg")
     ap.add_argument("--fused-levels", type=int, default=300, help="depth of the fused-unitary leg")
     ap.add_argument("--no-fused-tuned", action="store_true",
@@ -928,16 +933,20 @@ def main():
         print(json.dumps(run_fusion_wins(Q, W)))
         return
     if args.fusion_profile:
+        dt, tb = args.fusion_profile.split(":")
+        if dt not in ("c64", "c128"):
+            raise SystemExit("--fusion-profile: dtype must be c64 or c128")
         nets = W.blocked_circuit(28, 96, 7)
-        s = Q.Simulator(28, "c64", device=0, ckpt_interval=10 ** 6, fusion=Q.QTASK_FUSE_DENSE, fuse_width=5,
-                        tile_bits=10, low_bits=4, autotune=0)
+        s = Q.Simulator(28, dt, device=0, ckpt_interval=10 ** 6, fusion=Q.QTASK_FUSE_DENSE, fuse_width=5,
+                        tile_bits=int(tb), low_bits=4, autotune=0)
         try:
             s.build(nets)
             runs = [s.update(), s.update(full=True)]
         finally:
             s.close()
-        print(json.dumps({"workload": "blocked circuit, 28 qubits, 96 levels, complex64, every stage a dense 5-qubit "
-                                      "unitary on the matrix cores (b=10, c=4)",
+        print(json.dumps({"workload": "blocked circuit, 28 qubits, 96 levels, %s, every stage a dense 5-qubit "
+                                      "unitary on the matrix cores (b=%s, c=4)" % ({"c64": "complex64",
+                                                                                     "c128": "complex128"}[dt], tb),
                           "runs": [{"kernel_ms": r["kernel_ms"], "passes": r["passes"], "mfma_flops": r["mfma_flops"]}
                                    for r in runs]}))
         return
