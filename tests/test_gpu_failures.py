@@ -161,3 +161,43 @@ def test_allocator_hooks_hold_every_buffer():
     finally:
         s.close()
     assert fa.live == {}
+
+
+def test_misaligned_allocator_memory_is_refused():
+    """Memory from the allocator hook that is not 256-byte aligned is handed
+    back to the hook at once and the allocation fails (QTASK_E_NOMEM, the
+    reason in the last error), so no kernel reads through it; with aligned
+    memory the next update simulates normally."""
+    inner = Q.hip_allocator()
+    live = {}
+    shift = {"bytes": 16}
+
+    def alloc(nbytes):
+        p = inner._alloc(nbytes + 256)
+        if not p:
+            return 0
+        q = p + shift["bytes"]
+        live[q] = p
+        return q
+
+    def free(ptr):
+        inner._free(live.pop(ptr))
+
+    hooks = Q.DeviceAllocator(alloc, free)
+    n = 10
+    nets = W.layered_circuit(n, 6, 66)
+    s = Q.Simulator(n, "c128", allocator=hooks, device=0, ckpt_interval=4)
+    try:
+        s.build(nets)
+        with pytest.raises(Q.QtaskError) as e:
+            s.update()
+        assert e.value.code == Q.QTASK_E_NOMEM
+        assert "aligned" in Q.qtask_last_error(s.h)
+        assert live == {}
+        shift["bytes"] = 0
+        st = s.update()
+        assert st["mode"] == 1
+        check_state(s.state(), oracle.simulate(n, nets), "c128")
+    finally:
+        s.close()
+    assert live == {}
