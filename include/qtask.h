@@ -56,7 +56,7 @@ extern "C" {
 #define QTASK_E_NOMEM       4  /* device allocation failed, or a serving budget cannot admit the session */
 #define QTASK_E_DEVICE      5  /* a HIP call failed */
 #define QTASK_E_STALE       6  /* state queried while modifiers are pending since the last update */
-#define QTASK_E_UNSUPPORTED 7  /* valid request this build or this session mode does not support */
+#define QTASK_E_UNSUPPORTED 7  /* valid request that the library or this session mode does not support */
 #define QTASK_E_BUSY        8  /* the handle is owned by a server and has work in flight */
 
 typedef enum qtask_dtype {
