@@ -952,10 +952,11 @@ def main():
         return
     if args.serving_sweep:
         sweep = {"metric": "serving request latency against offered load", "unit": "ms",
-                 "workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels, "
-                             "one request of 1-3 edits each, Poisson arrivals at the offered rate",
-                 "c64": run_serving_sweep(Q, W, "c64", [8, 16, 32, 48]),
-                 "c128": run_serving_sweep(Q, W, "c128", [8, 16, 24])}
+                 "workload": "256 sessions, qubits log-uniform in [12,28], depth U{50..400} layered levels; "
+                             "per offered rate one Poisson stream of 128 requests of 1-3 edits over 128 sessions, "
+                             "then one request to every session at once",
+                 "c64": run_serving_curve(Q, W, "c64", [8, 16, 32, 48])[0],
+                 "c128": run_serving_curve(Q, W, "c128", [8, 16, 24])[0]}
         print(json.dumps(sweep))
         return
 
