@@ -16,6 +16,7 @@ WRITE_SIZE``, one pass each) of the same benchmark command, and writes
 Usage::
 
     python -m paper_2210_01076_amd.profiling mfma --trace DIR --pmc DIR --kernel NAME --out-txt FILE
+    python -m paper_2210_01076_amd.profiling issue --trace DIR --pmc DIR --kernel NAME [--block N] --out-txt FILE
     python -m paper_2210_01076_amd.profiling --trace DIR --fetch DIR --write DIR \\
         --bench-json FILE --counter-bench-json FILE --out-txt FILE --out-json FILE \\
         --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
@@ -233,7 +234,76 @@ def summarize_mfma(trace, pmc, kernel, command, last=0, cus=256, simds=4, xcds=8
     return rec, "\n".join(lines) + "\n"
 
 
+def summarize_issue(trace, pmc, kernel, command, block=0, cus=256, simds=4, xcds=8):
+    """Instruction mix and issue of one kernel from SQ counters: per-wave
+    instruction counts (SQ_INSTS_* / SQ_WAVES), the share of SIMD time the
+    VALU instructions occupy (a wave64 VALU instruction holds a 16-lane SIMD
+    for 4 cycles: SQ_INSTS_VALU x 4 / (cycles x CUs x SIMDs), cycles =
+    GRBM_GUI_ACTIVE / XCDs), and the wave-time ratios SQ_ACTIVE_INST_VALU /
+    SQ_WAVE_CYCLES and SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES.  Averages over all
+    dispatches of the kernel (with workgroup size `block` when given)."""
+    stats = kernel_stats(trace)
+    durs = []
+    with open(_one(trace, "kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            if _short(r["Kernel_Name"]) == kernel and (not block or int(r["Workgroup_Size_X"]) == block):
+                durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    per = defaultdict(list)
+    with open(_one(pmc, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if _short(r["Kernel_Name"]) == kernel and (not block or int(r["Workgroup_Size"]) == block):
+                per[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    avg = {k: _mean(v) for k, v in per.items()}
+    waves = avg.get("SQ_WAVES", float("nan"))
+    cycles = avg.get("GRBM_GUI_ACTIVE", float("nan")) / xcds
+    wave_cycles = avg.get("SQ_WAVE_CYCLES", float("nan"))
+    valu_share = avg.get("SQ_INSTS_VALU", float("nan")) * 4.0 / (cycles * cus * simds)
+    rec = {"kernel": kernel, "dispatches_traced": len(durs), "avg_duration_us": _mean(durs) / 1e3,
+           "counters": avg, "per_wave": {k: v / waves for k, v in avg.items() if k.startswith("SQ_INSTS_")},
+           "valu_issue_share": valu_share,
+           "active_valu_over_wave_cycles": avg.get("SQ_ACTIVE_INST_VALU", float("nan")) / wave_cycles,
+           "wait_inst_any_over_wave_cycles": avg.get("SQ_WAIT_INST_ANY", float("nan")) / wave_cycles,
+           "command": command}
+    lines = ["# %s -- instruction mix and issue" % kernel, ""]
+    for k, v in command.items():
+        lines.append("%s: %s" % (k, v))
+    lines += ["", "kernel statistics (rocprofv3 --stats):", "%-44s %7s %12s %12s %6s" % (
+        "kernel", "calls", "avg_us", "total_ms", "pct")]
+    for name, calls, a, tot, p in stats[:8]:
+        lines.append("%-44s %7d %12.2f %12.2f %6.2f" % (name[:44], calls, a / 1e3, tot / 1e6, p))
+    lines += ["", "%s%s: %d dispatches traced, avg %.2f us; %d with counters" % (
+        kernel, " (%d threads per workgroup)" % block if block else "", len(durs), _mean(durs) / 1e3,
+        len(next(iter(per.values()), []))), "counters per dispatch (averages):"]
+    for k in sorted(avg):
+        lines.append("  %-28s %.6g" % (k, avg[k]))
+    lines.append("per wave:")
+    for k, v in sorted(rec["per_wave"].items()):
+        lines.append("  %-28s %.1f" % (k, v))
+    lines += ["kernel cycles: GRBM_GUI_ACTIVE / %d XCDs = %.4g" % (xcds, cycles),
+              "VALU issue share of SIMD time: SQ_INSTS_VALU x 4 / (cycles x %d CUs x %d SIMDs) = %.3f" % (
+                  cus, simds, valu_share),
+              "SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES = %.3f" % rec["active_valu_over_wave_cycles"],
+              "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = %.3f" % rec["wait_inst_any_over_wave_cycles"]]
+    return rec, "\n".join(lines) + "\n"
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "issue":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("mode")
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--pmc", required=True)
+        ap.add_argument("--kernel", required=True)
+        ap.add_argument("--block", type=int, default=0)
+        ap.add_argument("--cmd-trace", default="")
+        ap.add_argument("--cmd-pmc", default="")
+        ap.add_argument("--out-txt", required=True)
+        a = ap.parse_args()
+        rec, txt = summarize_issue(a.trace, a.pmc, a.kernel, {"trace": a.cmd_trace, "pmc": a.cmd_pmc}, block=a.block)
+        with open(a.out_txt, "w") as f:
+            f.write(txt)
+        print(txt)
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "mfma":
         ap = argparse.ArgumentParser()
         ap.add_argument("mode")
