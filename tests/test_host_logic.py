@@ -794,10 +794,11 @@ def emulate_kernel(dump, n):
 
 
 @pytest.mark.parametrize("relabel", [0, 1])
-@pytest.mark.parametrize("n,b,c,fam,fusion", [
-    (8, 6, 2, "dense", 1), (9, 6, 3, "layered", 1), (10, 7, 4, "ladder", 1), (11, 7, 5, "layered", 1),
-    (10, 6, 4, "dense", 0), (12, 10, 3, "layered", 2)])
-def test_kernel_emulation_of_plan_blobs_matches_oracle(n, b, c, fam, fusion, relabel):
+@pytest.mark.parametrize("n,b,c,fam,fusion,k", [
+    (8, 6, 2, "dense", 1, 0), (9, 6, 3, "layered", 1, 0), (10, 7, 4, "ladder", 1, 0), (11, 7, 5, "layered", 1, 0),
+    (10, 6, 4, "dense", 0, 0), (12, 10, 3, "layered", 2, 5), (11, 10, 3, "layered", 2, 4),
+    (12, 11, 3, "dense", 2, 6)])
+def test_kernel_emulation_of_plan_blobs_matches_oracle(n, b, c, fam, fusion, k, relabel):
     """The blobs the kernel reads (maps, op records, coefficients) give the
     oracle's state when run as the kernel runs them, with and without
     relabelling passes, for list stages, dense 16x16 stages and matrix-core
@@ -810,7 +811,7 @@ def test_kernel_emulation_of_plan_blobs_matches_oracle(n, b, c, fam, fusion, rel
         nets = W.cp_ladder_circuit(n, 4, 92 + n)
     kw = dict(tile_bits=b, low_bits=c, ckpt_interval=5, relabel=relabel, fusion=fusion)
     if fusion == 2:
-        kw["fuse_width"] = 5
+        kw["fuse_width"] = k
     with plan_only(n, **kw) as sim:
         sim.build(nets)
         sim.update()
