@@ -864,6 +864,24 @@ def load_traffic(path):
     return rec.get("hbm_bytes_per_launch")
 
 
+def load_issue(path, launch_ms):
+    """The VALU-issue bound of the pass kernel from a committed SQ-counter
+    summary (the share of SIMD time its VALU instructions take, times the
+    traced launch time), beside the live launch time; None once the kernel
+    source no longer matches."""
+    if not path or not os.path.exists(path):
+        return None
+    from paper_2210_01076_amd import profiling
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != profiling.kernel_source_hash():
+        return None
+    bound_ms = rec["valu_bound_us"] / 1e3
+    return {"valu_issue_share": round(rec["valu_issue_share"], 4), "valu_bound_ms": round(bound_ms, 2),
+            "frac_of_valu_bound": round(bound_ms / launch_ms, 4) if launch_ms else None,
+            "source": os.path.relpath(path, ROOT)}
+
+
 def run_extras(Q, W, args):
     """The legs that do not fit the default run's time: the paper's other
     incremental protocols on the 24-qubit circuit, the 28-qubit layered
@@ -917,6 +935,7 @@ def main():
                     help="skip the autotuned comparison run of the fused-unitary leg (its timing candidates "
                          "would mix into a profile of the fused kernels)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_ladder_n32.json"))
+    ap.add_argument("--issue", default=os.path.join(ROOT, "profiles", "issue_ladder_n32.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the state and the serving sessions are not sharded across GPUs "
@@ -1073,7 +1092,8 @@ def main():
                      "kernel": "qk_pass<double, false>", "bytes_per_launch": head["launch_bytes"],
                      "avg_launch_ms": head["launch_ms"], "launches_timed": head["launches"],
                      "block": 1 << (b - 4),
-                     "scope": "every pass launch of the timed steps (32 qubits, complex128)"},
+                     "scope": "every pass launch of the timed steps (32 qubits, complex128)",
+                     "issue": load_issue(args.issue, head["launch_ms"])},
         "tier24": tier24,
         "fusion_wins": fusion_wins,
         "sparse_ckpt": sparse_ckpt,

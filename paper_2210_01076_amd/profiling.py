@@ -16,7 +16,8 @@ WRITE_SIZE``, one pass each) of the same benchmark command, and writes
 Usage::
 
     python -m paper_2210_01076_amd.profiling mfma --trace DIR --pmc DIR --kernel NAME --out-txt FILE
-    python -m paper_2210_01076_amd.profiling issue --trace DIR --pmc DIR --kernel NAME [--block N] --out-txt FILE
+    python -m paper_2210_01076_amd.profiling issue --trace DIR --pmc DIR --kernel NAME [--block N] --out-txt FILE \\
+        [--out-json FILE]
     python -m paper_2210_01076_amd.profiling --trace DIR --fetch DIR --write DIR \\
         --bench-json FILE --counter-bench-json FILE --out-txt FILE --out-json FILE \\
         --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
@@ -261,6 +262,8 @@ def summarize_issue(trace, pmc, kernel, command, block=0, cus=256, simds=4, xcds
     rec = {"kernel": kernel, "dispatches_traced": len(durs), "avg_duration_us": _mean(durs) / 1e3,
            "counters": avg, "per_wave": {k: v / waves for k, v in avg.items() if k.startswith("SQ_INSTS_")},
            "valu_issue_share": valu_share,
+           "valu_bound_us": valu_share * _mean(durs) / 1e3,
+           "kernel_source_hash": kernel_source_hash(),
            "active_valu_over_wave_cycles": avg.get("SQ_ACTIVE_INST_VALU", float("nan")) / wave_cycles,
            "wait_inst_any_over_wave_cycles": avg.get("SQ_WAIT_INST_ANY", float("nan")) / wave_cycles,
            "command": command}
@@ -283,7 +286,10 @@ def summarize_issue(trace, pmc, kernel, command, block=0, cus=256, simds=4, xcds
               "VALU issue share of SIMD time: SQ_INSTS_VALU x 4 / (cycles x %d CUs x %d SIMDs) = %.3f" % (
                   cus, simds, valu_share),
               "SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES = %.3f" % rec["active_valu_over_wave_cycles"],
-              "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = %.3f" % rec["wait_inst_any_over_wave_cycles"]]
+              "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = %.3f" % rec["wait_inst_any_over_wave_cycles"],
+              "time the VALU instructions alone take: %.2f of the %.2f us average launch" % (
+                  rec["valu_bound_us"], rec["avg_duration_us"]),
+              "kernel source hash: %s" % rec["kernel_source_hash"]]
     return rec, "\n".join(lines) + "\n"
 
 
@@ -298,10 +304,14 @@ def main():
         ap.add_argument("--cmd-trace", default="")
         ap.add_argument("--cmd-pmc", default="")
         ap.add_argument("--out-txt", required=True)
+        ap.add_argument("--out-json", default="")
         a = ap.parse_args()
         rec, txt = summarize_issue(a.trace, a.pmc, a.kernel, {"trace": a.cmd_trace, "pmc": a.cmd_pmc}, block=a.block)
         with open(a.out_txt, "w") as f:
             f.write(txt)
+        if a.out_json:
+            with open(a.out_json, "w") as f:
+                json.dump(rec, f, indent=1)
         print(txt)
         return
     if len(sys.argv) > 1 and sys.argv[1] == "mfma":

@@ -114,4 +114,6 @@ def test_issue_summary_ratios(tmp_path):
     assert rec["per_wave"]["SQ_INSTS_VALU"] == pytest.approx(100) and rec["per_wave"]["SQ_INSTS_SALU"] == 50
     assert rec["valu_issue_share"] == pytest.approx(400 * 4 / (1024 * 256 * 4))
     assert rec["wait_inst_any_over_wave_cycles"] == pytest.approx(0.25)
+    assert rec["valu_bound_us"] == pytest.approx(rec["valu_issue_share"] * 2.0)
+    assert rec["kernel_source_hash"] == profiling.kernel_source_hash()
     assert "VALU issue share of SIMD time" in txt
